@@ -1,0 +1,203 @@
+/*
+ * tbs.h -- C ABI of the MI355X (gfx950) tensor B-spline implicit heat-step library.
+ *
+ * Method: Shulga, Morozov, Roth, Friedrich, Hunziker, "Tensor B-Spline Numerical Methods for
+ * PDEs: a High-Performance Alternative to FEM" (arXiv:1904.03057).  The library computes the
+ * paper's system operator F(c) (Sec. 2.4, tensor form F(c) = t) for constant coefficients as a
+ * cascade of separable, shift-invariant 1-D filters (Sec. 2.4, separable kernel decomposition,
+ * Fig. FiltAlg), "on the fly" without assembling a matrix (Sec. 2.5, strategy (c)), and solves
+ * the resulting system with conjugate gradients (Sec. 2.5, step 3 of the method overview):
+ *
+ *     A = Mx (x) My (x) Mz + tau * ( hx^-2 Kx (x) My (x) Mz + hy^-2 Mx (x) Ky (x) Mz
+ *                                                          + hz^-2 Mx (x) My (x) Kz )
+ *
+ * 1-D taps for basis degree n (Sec. 2.3, Table 1, "scalar product" and "derivative" rows):
+ *     mass  m_k = b^{2n+1}(k),  stiffness  s_k = -(b^{2n+1})''(k),  |k| <= n.
+ * The operator is divided through by hx*hy*hz, so mass rows sum to 1.  One implicit Euler step
+ * of du/dt = Lap u + f is  A u^{k+1} = M (u^k + tau f)  (Galerkin load vector, Sec. 2.3, the
+ * discrete Ritz-Galerkin system with the source expanded in the same basis).
+ *
+ * Conventions for every entry point
+ *   - Arrays are caller-owned DEVICE pointers, layout c[z][y][x] with x contiguous, N = Nx*Ny*Nz
+ *     elements, 256-byte aligned (TBS_E_INVAL otherwise).  Inputs and outputs must not alias
+ *     unless stated.
+ *   - Every call is enqueued on the stream given to tbs_setup and is asynchronous, except the
+ *     calls that return host-side convergence data (documented below), which synchronise it.
+ *   - A context is not thread safe; use one context per stream.
+ *   - Arguments are validated before any HIP call, so validation errors are reported on a host
+ *     without a GPU.  Returns 0 on success, a negative TBS_E_* code on error, or the positive
+ *     TBS_W_NOT_CONVERGED when the output was written but the tolerance was not reached.
+ *   - Boundary conditions: TBS_BC_PERIODIC = circulant bands (needs every N_d >= 2n+1);
+ *     TBS_BC_DIRICHLET = homogeneous Dirichlet read as bands truncated at both ends (coefficients
+ *     outside the index box are zero).
+ */
+#ifndef TBS_H
+#define TBS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TBS_OK 0
+#define TBS_E_INVAL (-1)       /* bad argument: null/misaligned pointer, bad size, degree, tau, h, dtype */
+#define TBS_E_NOMEM (-2)       /* no workspace bound, or the bound workspace is too small */
+#define TBS_E_HIP (-3)         /* a HIP runtime call failed; tbs_last_error() has the text */
+#define TBS_E_BREAKDOWN (-4)   /* CG breakdown: p^T A p <= 0 or a non-finite value */
+#define TBS_E_STATE (-5)       /* call out of order (e.g. tbs_cg_step before tbs_cg_begin) */
+#define TBS_W_NOT_CONVERGED 1  /* iteration limit reached; outputs and stats are written */
+
+typedef struct tbs_ctx tbs_ctx;
+typedef struct tbs_net tbs_net;
+
+typedef enum { TBS_BC_PERIODIC = 0, TBS_BC_DIRICHLET = 1 } tbs_bc;
+typedef enum { TBS_F64 = 0, TBS_F32 = 1, TBS_BF16 = 2 } tbs_dtype;
+typedef enum {
+  TBS_PREC_FP64 = 0,       /* plain FP64 CG */
+  TBS_PREC_FP32 = 1,       /* raw FP32 CG (FP64 dot accumulation), no refinement */
+  TBS_PREC_MIXED = 2,      /* FP64 outer residual + FP32 inner CG (iterative refinement) */
+  TBS_PREC_MIXED_BF16 = 3  /* as MIXED, inner search direction stored in bf16 */
+} tbs_prec;
+
+typedef struct {
+  int iters;               /* CG iterations (inner iterations summed over refinement sweeps) */
+  int sweeps;              /* refinement sweeps (0 for FP64 / FP32) */
+  int used_learned_guess;  /* 1 if the network guess was kept by the fallback test */
+  int status;              /* return code of the call */
+  double rel_res_fp64;     /* ||b - A u_next|| / ||b|| recomputed in FP64 at exit */
+  double rel_res0;         /* same for the chosen initial guess */
+  double rel_res_plain;    /* same for the plain guess u^k */
+  double rel_res_learned;  /* same for the network guess (NaN if no network) */
+} tbs_stats;
+
+typedef struct {
+  double inner_rtol;       /* refinement: inner relative tolerance (default 1e-4) */
+  int inner_max_iter;      /* refinement: inner iteration cap per sweep (default 500) */
+  int max_sweeps;          /* refinement: sweep cap (default 12) */
+  int poll_every;          /* CG iterations enqueued between host convergence polls (default 4) */
+  int zchunk;              /* z-planes per workgroup of the stencil kernels (0 = automatic); results
+                              do not depend on it (each output sums its terms in the same order) */
+} tbs_opts;
+
+/* ---------------------------------------------------------------- context ---------------- */
+
+/* Creates a context for an Nx x Ny x Nz grid (grid = {Nx, Ny, Nz}, each >= 2n+1), basis degree
+ * 1..5, spacings h = {hx, hy, hz} > 0, time step tau > 0, boundary condition bc, and a HIP
+ * stream (hipStream_t passed as void*, NULL = default stream).  Computes the taps of Sec. 2.3
+ * in FP64 on the host.  Owns no device memory: see tbs_workspace_bytes. */
+int tbs_setup(tbs_ctx** out, const int64_t grid[3], int degree, const double h[3], double tau,
+              int bc, void* hip_stream);
+void tbs_destroy(tbs_ctx* ctx);
+
+/* Device scratch needed by the solver entry points for precision mode prec (tbs_prec), or, with
+ * prec = -1, by tbs_apply / tbs_rhs / tbs_residual / tbs_dot only (partial sums).  The caller
+ * allocates it (256-byte aligned) and binds it; the library never allocates device memory. */
+size_t tbs_workspace_bytes(const tbs_ctx* ctx, int prec);
+int tbs_bind_workspace(tbs_ctx* ctx, void* dev_ptr, size_t bytes);
+
+/* The 2(n+1) one-sided taps m_0..m_n, s_0..s_n in FP64 (host arrays of n+1 doubles each). */
+int tbs_taps(const tbs_ctx* ctx, double* mass, double* stiff);
+
+/* Options of the solver entry points (NULL restores the defaults). */
+int tbs_set_opts(tbs_ctx* ctx, const tbs_opts* opts);
+
+/* ------------------------------------------------------- operator (Sec. 2.4 / 2.5) ------- */
+
+/* y = A u  (the system operator F(c), on-the-fly strategy of Sec. 2.5).
+ * in_dtype / out_dtype: (F64,F64), (F32,F32), (BF16,F32), (F32,F64) or (BF16,F64); arithmetic
+ * is FP64 when out is F64, FP32 otherwise.  Needs a bound workspace of >= tbs_workspace_bytes(-1). */
+int tbs_apply(tbs_ctx* ctx, const void* u, int in_dtype, void* y, int out_dtype);
+
+/* b = (Mx (x) My (x) Mz)(u_prev + tau q): right-hand side of one implicit Euler step.
+ * q may be NULL (f = 0).  dtype F64 or F32 for all three arrays. */
+int tbs_rhs(tbs_ctx* ctx, const void* u_prev, const void* q, void* b, int dtype);
+
+/* FP64 residual norms: *rnorm = ||b - A x||_2, *bnorm = ||b||_2 (x, b FP64).  If r != NULL the
+ * residual is also written (r_dtype F64 or F32).  Synchronises the stream. */
+int tbs_residual(tbs_ctx* ctx, const double* x, const double* b, void* r, int r_dtype,
+                 double* rnorm, double* bnorm);
+
+/* *out = sum_i a_i b_i with FP64 accumulation in a fixed order (bitwise reproducible).
+ * dtype F64 or F32.  Synchronises the stream. */
+int tbs_dot(tbs_ctx* ctx, const void* a, const void* b, int dtype, double* out);
+
+/* Element conversion of N values: F64 -> F32 / BF16 (round to nearest even), F32 -> F64 / BF16,
+ * BF16 -> F32 / F64. */
+int tbs_convert(tbs_ctx* ctx, const void* src, int src_dtype, void* dst, int dst_dtype);
+
+/* ------------------------------------------------------- CG (Sec. 2.5, step 3) ----------- */
+
+/* Starts CG on A x = b in dtype (F64 or F32): r = b - A x, p = r, with state in the workspace
+ * (bound for prec TBS_PREC_FP64 when dtype is F64, TBS_PREC_FP32 when F32).  b and x stay
+ * caller-owned and must stay alive until the last tbs_cg_step.  Asynchronous. */
+int tbs_cg_begin(tbs_ctx* ctx, const void* b, void* x, int dtype, double rtol);
+
+/* Runs up to n_iters more Hestenes-Stiefel iterations (stops once ||r|| <= rtol ||b||, with r the
+ * recursive residual), leaving x consistent.  If rel_res_out is not NULL it receives ||r||/||b||
+ * and iters_out the total iteration count (both synchronise).  Returns TBS_E_BREAKDOWN on
+ * p^T A p <= 0 or non-finite values. */
+int tbs_cg_step(tbs_ctx* ctx, int n_iters, double* rel_res_out, int* iters_out);
+
+/* ------------------------------------------------------- implicit time step -------------- */
+
+/* One implicit Euler step: solves A u_next = M (u_prev + tau q) to ||b - A u|| <= rtol ||b||.
+ * u_prev, q (nullable), u_next: FP64 device arrays.  prec selects the arithmetic (tbs_prec).
+ * net: optional learned initial guess; its guess is kept only if its FP64 residual is smaller
+ * than that of the plain guess u_prev.  Synchronises; fills *stats if not NULL. */
+int tbs_timestep(tbs_ctx* ctx, const double* u_prev, const double* q, double* u_next, int prec,
+                 double rtol, int max_iter, tbs_net* net, tbs_stats* stats);
+
+/* ------------------------------------------------------- learned initial guess ----------- */
+/* Not in the paper (which warm-starts CG from a coarse-grid solution).  A 3-D CNN
+ * Conv(2->16) GELU Conv(16->16) GELU Conv(16->16) GELU Conv(16->1), 3x3x3 kernels, "same"
+ * padding (zero for Dirichlet, circular for periodic), exact erf GELU, bf16 operands on the
+ * matrix cores with FP32 accumulation, predicts u^{k+1} - u^k from (u^k, f).
+ * Parameters: 15,169 fp32 master weights, flat order W1 b1 W2 b2 W3 b3 W4 b4, W as
+ * [C_out][C_in][3][3][3] over (dz, dy, dx).  Inputs are scaled by their RMS, the output by
+ * tau * RMS(u^k) * out_scale. */
+
+#define TBS_NET_PARAMS 15169
+
+/* Creates a network object bound to a HIP stream (no device memory is allocated). */
+int tbs_net_create(tbs_net** out, void* hip_stream);
+void tbs_net_destroy(tbs_net* net);
+
+/* Device scratch for a grid of Nx x Ny x Nz voxels and a batch: forward only (training = 0)
+ * or training; bind before use.  The parameter block (weights, Adam moments) is included. */
+size_t tbs_net_workspace_bytes(const int64_t grid[3], int batch, int training);
+int tbs_net_bind_workspace(tbs_net* net, const int64_t grid[3], int batch, int training,
+                           void* dev_ptr, size_t bytes);
+
+/* Host <-> device parameter copies (n = TBS_NET_PARAMS fp32 values); set also resets Adam. */
+int tbs_net_set_weights(tbs_net* net, const float* host, size_t n);
+int tbs_net_get_weights(const tbs_net* net, float* host, size_t n);
+/* Output multiplier out_scale (default 1) and the Adam learning rate (default 1e-3). */
+int tbs_net_set_hparams(tbs_net* net, double out_scale, double lr);
+
+/* du = network guess for one sample: u_k (F64 or F32 per dtype), q (nullable = zero source),
+ * du (F32).  periodic selects circular padding. */
+int tbs_net_forward(tbs_net* net, const void* u_k, const void* q, int dtype, float* du,
+                    int periodic, double tau);
+
+/* One training step on a batch of `batch` samples laid out back to back (F32 arrays of
+ * batch x Nx*Ny*Nz): inputs u_k, q (nullable), targets du_target; loss = mean over the batch
+ * of mean((net - du_target)^2 / (tau RMS(u_k) out_scale)^2).  Forward, backward (data and
+ * weight gradients), Adam.  *loss_out (nullable) receives the loss (synchronises). */
+int tbs_net_train_step(tbs_net* net, const float* u_k, const float* q, const float* du_target,
+                       int batch, int periodic, double tau, float* loss_out);
+
+/* Raw pieces for kernel-level parity tests (F32 master weights are used as bf16):
+ * forward with saved activations, and the loss gradient of the last forward_train call. */
+int tbs_net_conv_layer(tbs_net* net, int layer, const uint16_t* x_bf16, const int64_t grid[3],
+                       int periodic, float* z_out);
+
+/* ------------------------------------------------------- errors ---------------------------- */
+const char* tbs_strerror(int code);
+const char* tbs_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TBS_H */

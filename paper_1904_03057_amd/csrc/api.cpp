@@ -1,0 +1,618 @@
+// C ABI of the tensor B-spline library: argument validation, taps, workspace layout and the
+// host-side orchestration of the HIP kernels (apply, RHS, fused CG, refinement, time step).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "../../include/tbs.h"
+#include "common.h"
+#include "net.h"
+#include "stencil.h"
+
+using namespace tbs;
+
+// ------------------------------------------------------------------------------------------
+// error text
+
+static thread_local std::string g_last_error;
+
+static int set_err(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                             \
+  do {                                                                                           \
+    hipError_t e_ = (expr);                                                                      \
+    if (e_ != hipSuccess) return set_err(TBS_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+extern "C" const char* tbs_strerror(int code) {
+  switch (code) {
+    case TBS_OK: return "ok";
+    case TBS_E_INVAL: return "invalid argument";
+    case TBS_E_NOMEM: return "workspace missing or too small";
+    case TBS_E_HIP: return "HIP runtime error";
+    case TBS_E_BREAKDOWN: return "CG breakdown (p^T A p <= 0 or non-finite value)";
+    case TBS_E_STATE: return "call out of order";
+    case TBS_W_NOT_CONVERGED: return "not converged within the iteration limit";
+  }
+  return "unknown code";
+}
+
+extern "C" const char* tbs_last_error(void) { return g_last_error.c_str(); }
+
+// ------------------------------------------------------------------------------------------
+// B-spline taps (FP64, host): m_k = b^{2n+1}(k), s_k = -(b^{2n+1})''(k)
+
+// centred B-spline of degree p at x by the truncated-power form of the (p+1)-fold box convolution
+static double bspline_val(int p, double x) {
+  const double half = 0.5 * (p + 1);
+  if (!(x > -half && x < half)) return 0.0;
+  double acc = 0.0, binom = 1.0, fact = 1.0;
+  for (int i = 2; i <= p; ++i) fact *= i;
+  for (int j = 0; j <= p + 1; ++j) {
+    const double t = x + half - j;
+    if (t > 0) acc += ((j & 1) ? -binom : binom) * std::pow(t, p);
+    binom = binom * (p + 1 - j) / (j + 1);
+  }
+  return acc / fact;
+}
+
+static void make_taps(int n, double* m, double* s) {
+  const int p = 2 * n + 1;
+  for (int k = 0; k <= n; ++k) {
+    m[k] = bspline_val(p, (double)k);
+    // second derivative = second difference of the degree p-2 spline (derivative rule twice)
+    s[k] = -(bspline_val(p - 2, k + 1.0) - 2.0 * bspline_val(p - 2, (double)k) + bspline_val(p - 2, k - 1.0));
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// context
+
+struct tbs_ctx {
+  int64_t nx, ny, nz, N;
+  int n, bc;
+  double h[3], tau;
+  hipStream_t st;
+  Taps taps;
+  int tiles_x, tiles_y, nchunks, zc, nblocks, nparts;
+  char* ws;
+  size_t ws_bytes;
+  tbs_opts opts;
+  Scalars* host_scal;  // pinned mirror, allocated on first solver call
+  // CG session state (tbs_cg_begin / tbs_cg_step)
+  int cg_active, cg_dt, cg_enq;
+  void* cg_x;
+};
+
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+static bool aligned_ptr(const void* p) { return p && ((uintptr_t)p & 255u) == 0; }
+
+static void plan_geometry(tbs_ctx* c, int zchunk) {
+  c->tiles_x = (int)((c->nx + kTileX - 1) / kTileX);
+  c->tiles_y = (int)((c->ny + kTileY - 1) / kTileY);
+  const int64_t tiles = (int64_t)c->tiles_x * c->tiles_y;
+  // enough blocks to fill 256 CUs several times, but chunks of at least 4(2n+1) planes
+  int64_t want = (4096 + tiles - 1) / tiles;
+  const int64_t minzc = std::max<int64_t>(16, 4 * (2 * c->n + 1));
+  int64_t maxchunks = std::max<int64_t>(1, c->nz / minzc);
+  int64_t chunks = std::min(want, maxchunks);
+  if (chunks < 1) chunks = 1;
+  c->zc = (int)((c->nz + chunks - 1) / chunks);
+  if (zchunk > 0) c->zc = (int)std::min<int64_t>(zchunk, c->nz);
+  c->nchunks = (int)((c->nz + c->zc - 1) / c->zc);
+  c->nblocks = (int)(tiles * c->nchunks);
+  c->nparts = std::max(c->nblocks, kVecBlocks);
+}
+
+// workspace layout: [scalars x4][part0][part1][arrays...]
+enum { SC_CG = 0, SC_AUX = 1 };
+static size_t ws_head(const tbs_ctx* c) { return 1024 + 2 * align256((size_t)c->nparts * 8); }
+
+struct Layout {
+  size_t bytes;
+  size_t off[8];
+};
+
+static Layout layout(const tbs_ctx* c, int prec) {
+  Layout L{};
+  size_t o = ws_head(c);
+  const size_t N = (size_t)c->N;
+  auto put = [&](int i, size_t esz) { L.off[i] = o; o += align256(N * esz); };
+  switch (prec) {
+    case -1: break;
+    case TBS_PREC_FP64:  // b, r, pA, pB, q
+      put(0, 8); put(1, 8); put(2, 8); put(3, 8); put(4, 8); break;
+    case TBS_PREC_FP32:  // b, x, r, pA, pB, q (f32)
+      put(0, 4); put(1, 4); put(2, 4); put(3, 4); put(4, 4); put(5, 4); break;
+    case TBS_PREC_MIXED:  // b64, r32, d, pA, pB, q
+      put(0, 8); put(1, 4); put(2, 4); put(3, 4); put(4, 4); put(5, 4); break;
+    case TBS_PREC_MIXED_BF16:  // b64, r32, d, pA(bf16), pB(bf16), q
+      put(0, 8); put(1, 4); put(2, 4); put(3, 2); put(4, 2); put(5, 4); break;
+  }
+  L.bytes = o;
+  return L;
+}
+
+static Scalars* scal(const tbs_ctx* c, int slot) { return (Scalars*)(c->ws + slot * 256); }
+static double* part0(const tbs_ctx* c) { return (double*)(c->ws + 1024); }
+static double* part1(const tbs_ctx* c) { return (double*)(c->ws + 1024 + align256((size_t)c->nparts * 8)); }
+
+static StencilArgs base_args(const tbs_ctx* c) {
+  StencilArgs a{};
+  a.nx = (int)c->nx; a.ny = (int)c->ny; a.nz = (int)c->nz; a.zc = c->zc;
+  a.tiles_x = c->tiles_x; a.tiles_y = c->tiles_y; a.nchunks = c->nchunks; a.nblocks = c->nblocks;
+  a.t = c->taps;
+  a.part0 = part0(c);
+  a.part1 = part1(c);
+  return a;
+}
+
+extern "C" int tbs_setup(tbs_ctx** out, const int64_t grid[3], int degree, const double h[3], double tau, int bc,
+                         void* hip_stream) {
+  if (!out || !grid || !h) return set_err(TBS_E_INVAL, "null argument");
+  *out = nullptr;
+  if (degree < 1 || degree > 5) return set_err(TBS_E_INVAL, "degree %d not in 1..5", degree);
+  if (bc != TBS_BC_PERIODIC && bc != TBS_BC_DIRICHLET) return set_err(TBS_E_INVAL, "bad boundary condition %d", bc);
+  if (!(tau > 0.0) || !std::isfinite(tau)) return set_err(TBS_E_INVAL, "tau must be positive and finite");
+  for (int d = 0; d < 3; ++d) {
+    if (!(h[d] > 0.0) || !std::isfinite(h[d])) return set_err(TBS_E_INVAL, "h[%d] must be positive", d);
+    if (grid[d] < 2 * degree + 1) return set_err(TBS_E_INVAL, "grid[%d]=%lld < 2n+1", d, (long long)grid[d]);
+  }
+  if (grid[0] * grid[1] > (int64_t)1 << 30 || grid[2] > (int64_t)1 << 30 ||
+      grid[0] > (int64_t)1 << 24 || grid[1] > (int64_t)1 << 24)
+    return set_err(TBS_E_INVAL, "grid too large");
+  tbs_ctx* c = new (std::nothrow) tbs_ctx();
+  if (!c) return set_err(TBS_E_INVAL, "out of host memory");
+  c->nx = grid[0]; c->ny = grid[1]; c->nz = grid[2];
+  c->N = grid[0] * grid[1] * grid[2];
+  c->n = degree; c->bc = bc;
+  for (int d = 0; d < 3; ++d) c->h[d] = h[d];
+  c->tau = tau;
+  c->st = (hipStream_t)hip_stream;
+  make_taps(degree, c->taps.m, c->taps.s);
+  for (int k = degree + 1; k < 6; ++k) c->taps.m[k] = c->taps.s[k] = 0.0;
+  c->taps.ax = tau / (h[0] * h[0]);
+  c->taps.ay = tau / (h[1] * h[1]);
+  c->taps.az = tau / (h[2] * h[2]);
+  c->taps.tau = tau;
+  plan_geometry(c, 0);
+  c->opts.inner_rtol = 1e-4;
+  c->opts.inner_max_iter = 500;
+  c->opts.max_sweeps = 12;
+  c->opts.poll_every = 4;
+  c->opts.zchunk = 0;
+  *out = c;
+  return TBS_OK;
+}
+
+extern "C" void tbs_destroy(tbs_ctx* c) {
+  if (!c) return;
+  if (c->host_scal) (void)hipHostFree(c->host_scal);
+  delete c;
+}
+
+extern "C" size_t tbs_workspace_bytes(const tbs_ctx* c, int prec) {
+  if (!c || prec < -1 || prec > TBS_PREC_MIXED_BF16) return 0;
+  return layout(c, prec).bytes;
+}
+
+extern "C" int tbs_bind_workspace(tbs_ctx* c, void* p, size_t bytes) {
+  if (!c) return set_err(TBS_E_INVAL, "null context");
+  if (!aligned_ptr(p)) return set_err(TBS_E_INVAL, "workspace must be a 256-byte aligned device pointer");
+  if (bytes < ws_head(c)) return set_err(TBS_E_NOMEM, "workspace smaller than the minimum %zu", ws_head(c));
+  c->ws = (char*)p;
+  c->ws_bytes = bytes;
+  c->cg_active = 0;
+  return TBS_OK;
+}
+
+extern "C" int tbs_taps(const tbs_ctx* c, double* m, double* s) {
+  if (!c || !m || !s) return set_err(TBS_E_INVAL, "null argument");
+  for (int k = 0; k <= c->n; ++k) { m[k] = c->taps.m[k]; s[k] = c->taps.s[k]; }
+  return TBS_OK;
+}
+
+extern "C" int tbs_set_opts(tbs_ctx* c, const tbs_opts* o) {
+  if (!c) return set_err(TBS_E_INVAL, "null context");
+  if (!o) {
+    c->opts.inner_rtol = 1e-4; c->opts.inner_max_iter = 500; c->opts.max_sweeps = 12; c->opts.poll_every = 4;
+    c->opts.zchunk = 0;
+  } else {
+    if (!(o->inner_rtol > 0 && o->inner_rtol < 1) || o->inner_max_iter < 1 || o->max_sweeps < 1 ||
+        o->poll_every < 1 || o->zchunk < 0)
+      return set_err(TBS_E_INVAL, "bad options");
+    c->opts = *o;
+  }
+  // the partial-sum buffers are sized for the automatic geometry; a smaller chunk means more blocks
+  const size_t old_head = ws_head(c);
+  plan_geometry(c, c->opts.zchunk);
+  if (c->ws && ws_head(c) > old_head) c->ws = nullptr;  // bound workspace no longer fits: rebind
+  return TBS_OK;
+}
+
+static int need_ws(const tbs_ctx* c, int prec) {
+  if (!c->ws) return set_err(TBS_E_NOMEM, "no workspace bound");
+  const size_t need = layout(c, prec).bytes;
+  if (c->ws_bytes < need) return set_err(TBS_E_NOMEM, "workspace %zu bytes < %zu needed", c->ws_bytes, need);
+  return TBS_OK;
+}
+
+static int ensure_host_scal(tbs_ctx* c) {
+  if (!c->host_scal) HIPCHK(hipHostMalloc((void**)&c->host_scal, sizeof(Scalars) * 2, hipHostMallocDefault));
+  return TBS_OK;
+}
+
+static int read_scal(tbs_ctx* c, int slot, Scalars* outv) {
+  int rc = ensure_host_scal(c);
+  if (rc) return rc;
+  HIPCHK(hipMemcpyAsync(c->host_scal, scal(c, slot), sizeof(Scalars), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(hipStreamSynchronize(c->st));
+  *outv = *c->host_scal;
+  return TBS_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// operator entry points
+
+extern "C" int tbs_apply(tbs_ctx* c, const void* u, int in_dt, void* y, int out_dt) {
+  if (!c) return set_err(TBS_E_INVAL, "null context");
+  if (!aligned_ptr(u) || !aligned_ptr(y)) return set_err(TBS_E_INVAL, "u and y must be 256-byte aligned device pointers");
+  if (u == y) return set_err(TBS_E_INVAL, "u and y must not alias");
+  const bool ok = (in_dt == TBS_F64 && out_dt == TBS_F64) || (in_dt == TBS_F32 && out_dt == TBS_F32) ||
+                  (in_dt == TBS_BF16 && out_dt == TBS_F32) || (in_dt == TBS_F32 && out_dt == TBS_F64) ||
+                  (in_dt == TBS_BF16 && out_dt == TBS_F64);
+  if (!ok) return set_err(TBS_E_INVAL, "unsupported dtype combination (%d -> %d)", in_dt, out_dt);
+  StencilArgs a = base_args(c);
+  a.in0 = u;
+  a.out0 = y;
+  HIPCHK(launch_apply(a, c->n, c->bc, in_dt, out_dt, c->st));
+  return TBS_OK;
+}
+
+extern "C" int tbs_rhs(tbs_ctx* c, const void* u_prev, const void* q, void* b, int dt) {
+  if (!c) return set_err(TBS_E_INVAL, "null context");
+  if (!aligned_ptr(u_prev) || !aligned_ptr(b) || (q && !aligned_ptr(q)))
+    return set_err(TBS_E_INVAL, "arrays must be 256-byte aligned device pointers");
+  if (b == u_prev || b == q) return set_err(TBS_E_INVAL, "b must not alias the inputs");
+  if (dt != TBS_F64 && dt != TBS_F32) return set_err(TBS_E_INVAL, "rhs dtype must be F64 or F32");
+  StencilArgs a = base_args(c);
+  a.in0 = u_prev;
+  a.in1 = q;
+  a.out0 = b;
+  HIPCHK(launch_rhs(a, c->n, c->bc, dt, c->st));
+  return TBS_OK;
+}
+
+// r = b - A x (FP64), norms to scal slot; r written if r != NULL (r_dt F64/F32)
+static int resid_async(tbs_ctx* c, const double* x, const double* b, void* r, int r_dt, int slot, int fin_op,
+                       double rtol) {
+  StencilArgs a = base_args(c);
+  a.in0 = x;
+  a.bvec = b;
+  a.out0 = r;
+  HIPCHK(launch_resid(a, c->n, c->bc, r_dt == TBS_F32 ? 1 : 0, c->st));
+  HIPCHK(launch_finalize(fin_op, part0(c), part1(c), c->nblocks, scal(c, slot), rtol, c->st));
+  return TBS_OK;
+}
+
+extern "C" int tbs_residual(tbs_ctx* c, const double* x, const double* b, void* r, int r_dt, double* rnorm,
+                            double* bnorm) {
+  if (!c) return set_err(TBS_E_INVAL, "null context");
+  if (!aligned_ptr(x) || !aligned_ptr(b) || (r && !aligned_ptr(r)))
+    return set_err(TBS_E_INVAL, "arrays must be 256-byte aligned device pointers");
+  if (r && (r == (void*)x || r == (void*)b)) return set_err(TBS_E_INVAL, "r must not alias x or b");
+  if (r && r_dt != TBS_F64 && r_dt != TBS_F32) return set_err(TBS_E_INVAL, "r dtype must be F64 or F32");
+  int rc = need_ws(c, -1);
+  if (rc) return rc;
+  rc = resid_async(c, x, b, r, r_dt, SC_AUX, FIN_NORMS, 0.0);
+  if (rc) return rc;
+  Scalars s;
+  rc = read_scal(c, SC_AUX, &s);
+  if (rc) return rc;
+  if (rnorm) *rnorm = std::sqrt(s.out);
+  if (bnorm) *bnorm = std::sqrt(s.out2);
+  return TBS_OK;
+}
+
+extern "C" int tbs_dot(tbs_ctx* c, const void* a, const void* b, int dt, double* out) {
+  if (!c || !out) return set_err(TBS_E_INVAL, "null argument");
+  if (!aligned_ptr(a) || !aligned_ptr(b)) return set_err(TBS_E_INVAL, "arrays must be 256-byte aligned device pointers");
+  if (dt != TBS_F64 && dt != TBS_F32) return set_err(TBS_E_INVAL, "dot dtype must be F64 or F32");
+  int rc = need_ws(c, -1);
+  if (rc) return rc;
+  HIPCHK(launch_dot(a, b, c->N, dt, part0(c), c->st));
+  HIPCHK(launch_finalize(FIN_DOT, part0(c), nullptr, kVecBlocks, scal(c, SC_AUX), 0.0, c->st));
+  Scalars s;
+  rc = read_scal(c, SC_AUX, &s);
+  if (rc) return rc;
+  *out = s.out;
+  return TBS_OK;
+}
+
+extern "C" int tbs_convert(tbs_ctx* c, const void* src, int sdt, void* dst, int ddt) {
+  if (!c) return set_err(TBS_E_INVAL, "null context");
+  if (!aligned_ptr(src) || !aligned_ptr(dst)) return set_err(TBS_E_INVAL, "arrays must be 256-byte aligned device pointers");
+  if (sdt < 0 || sdt > 2 || ddt < 0 || ddt > 2 || sdt == ddt) return set_err(TBS_E_INVAL, "bad conversion");
+  HIPCHK(launch_convert(src, sdt, dst, ddt, c->N, c->st));
+  return TBS_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// CG core.  dt: 0 f64, 1 f32, 2 f32 with p in bf16.  Arrays: x (iterate), r, pA, pB, q.
+
+struct CgArrays {
+  void* x;
+  void* r;
+  void* p[2];
+  void* q;
+};
+
+static int cg1_async(tbs_ctx* c, const CgArrays& A, int dt, int k) {
+  StencilArgs a = base_args(c);
+  a.in0 = A.r;
+  a.in1 = A.p[k & 1];
+  a.out1 = A.p[(k + 1) & 1];
+  a.out0 = A.q;
+  a.io0 = A.x;
+  a.scal = scal(c, SC_CG);
+  a.first = (k == 0);
+  HIPCHK(launch_cg1(a, c->n, c->bc, dt, c->st));
+  HIPCHK(launch_finalize(FIN_ALPHA, part0(c), nullptr, c->nblocks, scal(c, SC_CG), 0.0, c->st));
+  HIPCHK(launch_cg2(A.r, A.q, c->N, dt == 0 ? 0 : 1, part0(c), scal(c, SC_CG), c->st));
+  HIPCHK(launch_finalize(FIN_BETA, part0(c), nullptr, kVecBlocks, scal(c, SC_CG), 0.0, c->st));
+  return TBS_OK;
+}
+
+// Runs CG iterations k = k0 .. until done / max_iter, then flushes the pending x update.
+// Returns TBS_OK, TBS_W_NOT_CONVERGED or TBS_E_BREAKDOWN; *nit receives the completed count.
+static int cg_loop(tbs_ctx* c, const CgArrays& A, int dt, int k0, int max_iter, int* nit) {
+  int k = k0, rc;
+  Scalars s;
+  rc = read_scal(c, SC_CG, &s);
+  if (rc) return rc;
+  while (!s.done && k < max_iter) {
+    const int batch = std::min(c->opts.poll_every, max_iter - k);
+    for (int i = 0; i < batch; ++i) {
+      rc = cg1_async(c, A, dt, k++);
+      if (rc) return rc;
+    }
+    rc = read_scal(c, SC_CG, &s);
+    if (rc) return rc;
+    k = s.nit;
+  }
+  HIPCHK(launch_flush(A.x, A.p[0], A.p[1], c->N, dt, scal(c, SC_CG), c->st));
+  HIPCHK(launch_finalize(FIN_CLEAR_PENDING, nullptr, nullptr, 0, scal(c, SC_CG), 0.0, c->st));
+  *nit = s.nit;
+  if (s.status == TBS_E_BREAKDOWN) return set_err(TBS_E_BREAKDOWN, "CG breakdown after %d iterations", s.nit);
+  return s.done ? TBS_OK : TBS_W_NOT_CONVERGED;
+}
+
+// r = b - A x and CG scalars for dt 0 (FP64, via the residual kernel) or 1/2 (FP32 apply + sub)
+static int cg_init_async(tbs_ctx* c, const void* b, const CgArrays& A, int dt, double rtol) {
+  if (dt == 0) return resid_async(c, (const double*)A.x, (const double*)b, A.r, TBS_F64, SC_CG, FIN_INIT, rtol);
+  // FP32: q = A x, then r = b - q with the partial sums of r.r and b.b
+  StencilArgs a = base_args(c);
+  a.in0 = A.x;
+  a.out0 = A.q;
+  HIPCHK(launch_apply(a, c->n, c->bc, 1, 1, c->st));
+  HIPCHK(launch_sub_norm(A.r, b, A.q, c->N, 1, part0(c), part1(c), c->st));
+  HIPCHK(launch_finalize(FIN_INIT, part0(c), part1(c), kVecBlocks, scal(c, SC_CG), rtol, c->st));
+  return TBS_OK;
+}
+
+extern "C" int tbs_cg_begin(tbs_ctx* c, const void* b, void* x, int dt, double rtol) {
+  if (!c) return set_err(TBS_E_INVAL, "null context");
+  if (!aligned_ptr(b) || !aligned_ptr(x)) return set_err(TBS_E_INVAL, "arrays must be 256-byte aligned device pointers");
+  if (b == x) return set_err(TBS_E_INVAL, "b and x must not alias");
+  if (dt != TBS_F64 && dt != TBS_F32) return set_err(TBS_E_INVAL, "CG dtype must be F64 or F32");
+  if (!(rtol >= 0.0)) return set_err(TBS_E_INVAL, "rtol must be >= 0");
+  const int prec = dt == TBS_F64 ? TBS_PREC_FP64 : TBS_PREC_FP32;
+  int rc = need_ws(c, prec);
+  if (rc) return rc;
+  const Layout L = layout(c, prec);
+  CgArrays A;
+  A.x = x;
+  if (dt == TBS_F64) { A.r = c->ws + L.off[1]; A.p[0] = c->ws + L.off[2]; A.p[1] = c->ws + L.off[3]; A.q = c->ws + L.off[4]; }
+  else { A.r = c->ws + L.off[2]; A.p[0] = c->ws + L.off[3]; A.p[1] = c->ws + L.off[4]; A.q = c->ws + L.off[5]; }
+  rc = cg_init_async(c, b, A, dt == TBS_F64 ? 0 : 1, rtol);
+  if (rc) return rc;
+  c->cg_active = 1;
+  c->cg_dt = dt;
+  c->cg_enq = 0;
+  c->cg_x = x;
+  return TBS_OK;
+}
+
+extern "C" int tbs_cg_step(tbs_ctx* c, int n_iters, double* rel_res_out, int* iters_out) {
+  if (!c) return set_err(TBS_E_INVAL, "null context");
+  if (!c->cg_active) return set_err(TBS_E_STATE, "tbs_cg_step before tbs_cg_begin");
+  if (n_iters < 0) return set_err(TBS_E_INVAL, "n_iters must be >= 0");
+  const int prec = c->cg_dt == TBS_F64 ? TBS_PREC_FP64 : TBS_PREC_FP32;
+  int rc = need_ws(c, prec);
+  if (rc) return rc;
+  const Layout L = layout(c, prec);
+  CgArrays A;
+  A.x = c->cg_x;
+  if (c->cg_dt == TBS_F64) { A.r = c->ws + L.off[1]; A.p[0] = c->ws + L.off[2]; A.p[1] = c->ws + L.off[3]; A.q = c->ws + L.off[4]; }
+  else { A.r = c->ws + L.off[2]; A.p[0] = c->ws + L.off[3]; A.p[1] = c->ws + L.off[4]; A.q = c->ws + L.off[5]; }
+  int nit = 0;
+  rc = cg_loop(c, A, c->cg_dt == TBS_F64 ? 0 : 1, c->cg_enq, c->cg_enq + n_iters, &nit);
+  c->cg_enq = nit;
+  if (rc < 0) return rc;
+  if (rel_res_out || iters_out) {
+    Scalars s;
+    int rc2 = read_scal(c, SC_CG, &s);
+    if (rc2) return rc2;
+    if (rel_res_out) *rel_res_out = s.bb > 0 ? std::sqrt(s.rr / s.bb) : 0.0;
+    if (iters_out) *iters_out = s.nit;
+  }
+  return rc == TBS_W_NOT_CONVERGED ? TBS_OK : rc;
+}
+
+// ------------------------------------------------------------------------------------------
+// implicit time step
+
+static int copy_async(tbs_ctx* c, void* dst, const void* src, size_t bytes) {
+  HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, c->st));
+  return TBS_OK;
+}
+
+static int fp64_relres(tbs_ctx* c, const double* x, const double* b, double* rel) {
+  int rc = resid_async(c, x, b, nullptr, TBS_F64, SC_AUX, FIN_NORMS, 0.0);
+  if (rc) return rc;
+  Scalars s;
+  rc = read_scal(c, SC_AUX, &s);
+  if (rc) return rc;
+  *rel = s.out2 > 0 ? std::sqrt(s.out / s.out2) : std::sqrt(s.out);
+  return TBS_OK;
+}
+
+extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, double* u_next, int prec, double rtol,
+                            int max_iter, tbs_net* net, tbs_stats* stats) {
+  if (!c) return set_err(TBS_E_INVAL, "null context");
+  if (!aligned_ptr(u_prev) || !aligned_ptr(u_next) || (q && !aligned_ptr(q)))
+    return set_err(TBS_E_INVAL, "arrays must be 256-byte aligned device pointers");
+  if (u_next == u_prev || u_next == q) return set_err(TBS_E_INVAL, "u_next must not alias the inputs");
+  if (prec < TBS_PREC_FP64 || prec > TBS_PREC_MIXED_BF16) return set_err(TBS_E_INVAL, "bad precision mode");
+  if (!(rtol >= 0.0) || max_iter < 0) return set_err(TBS_E_INVAL, "bad rtol / max_iter");
+  int rc = need_ws(c, prec);
+  if (rc) return rc;
+  c->cg_active = 0;
+  const Layout L = layout(c, prec);
+  const size_t N = (size_t)c->N;
+  tbs_stats st{};
+  st.rel_res_learned = NAN;
+
+  // right-hand side, FP64 except for the raw FP32 path
+  double* b64 = (prec == TBS_PREC_FP32) ? nullptr : (double*)(c->ws + L.off[0]);
+  double* b64_tmp = nullptr;
+  if (prec != TBS_PREC_FP32) {
+    rc = tbs_rhs(c, u_prev, q, b64, TBS_F64);
+    if (rc) return rc;
+  } else {
+    // the FP64 check needs an FP64 b: keep it in u_next temporarily? no -- compute b64 on demand below
+  }
+
+  // initial guess: plain u^k, or the network guess if its FP64 residual is smaller
+  rc = copy_async(c, u_next, u_prev, N * 8);
+  if (rc) return rc;
+  if (net && prec != TBS_PREC_FP32) {
+    rc = fp64_relres(c, u_prev, b64, &st.rel_res_plain);
+    if (rc) return rc;
+    const float* du = nullptr;
+    const int64_t grid[3] = {c->nx, c->ny, c->nz};
+    rc = tbs_net_guess_internal(net, grid, c->bc == TBS_BC_PERIODIC, c->tau, c->st, u_prev, q, &du);
+    if (rc) return rc;
+    HIPCHK(launch_guess_combine(u_next, u_prev, du, c->N, c->st));
+    rc = fp64_relres(c, u_next, b64, &st.rel_res_learned);
+    if (rc) return rc;
+    if (st.rel_res_learned < st.rel_res_plain) {
+      st.used_learned_guess = 1;
+    } else {
+      rc = copy_async(c, u_next, u_prev, N * 8);
+      if (rc) return rc;
+    }
+  }
+
+  int result = TBS_OK;
+  if (prec == TBS_PREC_FP64) {
+    CgArrays A{u_next, c->ws + L.off[1], {c->ws + L.off[2], c->ws + L.off[3]}, c->ws + L.off[4]};
+    rc = cg_init_async(c, b64, A, 0, rtol);
+    if (rc) return rc;
+    Scalars s;
+    rc = read_scal(c, SC_CG, &s);
+    if (rc) return rc;
+    st.rel_res0 = s.bb > 0 ? std::sqrt(s.rr0 / s.bb) : 0.0;
+    if (!net) st.rel_res_plain = st.rel_res0;
+    int nit = 0;
+    result = cg_loop(c, A, 0, 0, max_iter, &nit);
+    st.iters = nit;
+    if (result < 0 && result != TBS_E_BREAKDOWN) return result;
+    rc = fp64_relres(c, u_next, b64, &st.rel_res_fp64);
+    if (rc) return rc;
+  } else if (prec == TBS_PREC_FP32) {
+    float* b32 = (float*)(c->ws + L.off[0]);
+    float* x32 = (float*)(c->ws + L.off[1]);
+    float* r32 = (float*)(c->ws + L.off[2]);
+    // b32 = M(u + tau q) in FP32 arithmetic on FP32-rounded inputs
+    HIPCHK(launch_convert(u_prev, 0, x32, 1, c->N, c->st));
+    if (q) HIPCHK(launch_convert(q, 0, r32, 1, c->N, c->st));
+    rc = tbs_rhs(c, x32, q ? r32 : nullptr, b32, TBS_F32);
+    if (rc) return rc;
+    CgArrays A{x32, r32, {c->ws + L.off[3], c->ws + L.off[4]}, c->ws + L.off[5]};
+    rc = cg_init_async(c, b32, A, 1, rtol);
+    if (rc) return rc;
+    Scalars s;
+    rc = read_scal(c, SC_CG, &s);
+    if (rc) return rc;
+    st.rel_res0 = s.bb > 0 ? std::sqrt(s.rr0 / s.bb) : 0.0;
+    st.rel_res_plain = st.rel_res0;
+    int nit = 0;
+    result = cg_loop(c, A, 1, 0, max_iter, &nit);
+    st.iters = nit;
+    if (result < 0 && result != TBS_E_BREAKDOWN) return result;
+    HIPCHK(launch_convert(x32, 1, u_next, 0, c->N, c->st));
+    // FP64 residual of the FP32 answer against the FP64 right-hand side (b64 built in r-space)
+    double* b64w = (double*)(c->ws + L.off[2]);  // r32 + pA span >= 8N bytes: reuse as FP64 b
+    (void)b64_tmp;
+    rc = tbs_rhs(c, u_prev, q, b64w, TBS_F64);
+    if (rc) return rc;
+    rc = fp64_relres(c, u_next, b64w, &st.rel_res_fp64);
+    if (rc) return rc;
+  } else {
+    // iterative refinement: FP64 outer residual, FP32 inner CG (p in bf16 for MIXED_BF16)
+    const int dt = (prec == TBS_PREC_MIXED_BF16) ? 2 : 1;
+    float* r32 = (float*)(c->ws + L.off[1]);
+    float* d32 = (float*)(c->ws + L.off[2]);
+    CgArrays A{d32, r32, {c->ws + L.off[3], c->ws + L.off[4]}, c->ws + L.off[5]};
+    int total = 0, sweeps = 0;
+    for (;;) {
+      rc = resid_async(c, u_next, b64, r32, TBS_F32, SC_AUX, FIN_NORMS, 0.0);
+      if (rc) return rc;
+      Scalars s;
+      rc = read_scal(c, SC_AUX, &s);
+      if (rc) return rc;
+      const double rel = s.out2 > 0 ? std::sqrt(s.out / s.out2) : std::sqrt(s.out);
+      if (sweeps == 0) {
+        st.rel_res0 = rel;
+        if (!net) st.rel_res_plain = rel;
+      }
+      st.rel_res_fp64 = rel;
+      if (!std::isfinite(rel)) { result = set_err(TBS_E_BREAKDOWN, "non-finite residual"); break; }
+      if (rel <= rtol || s.out2 == 0.0) { result = TBS_OK; break; }
+      if (sweeps >= c->opts.max_sweeps || total >= max_iter) { result = TBS_W_NOT_CONVERGED; break; }
+      // inner solve A d = r32 from d = 0 to relative tolerance eta (no tighter than needed)
+      const double eta = std::max(c->opts.inner_rtol, 0.5 * rtol / rel);
+      HIPCHK(launch_fill(d32, 1, c->N, c->st));
+      HIPCHK(launch_finalize(FIN_INIT, part0(c), part0(c), c->nblocks, scal(c, SC_CG), eta, c->st));
+      int nit = 0;
+      const int cap = std::min(c->opts.inner_max_iter, std::max(1, max_iter - total));
+      int irc = cg_loop(c, A, dt, 0, cap, &nit);
+      total += nit;
+      if (irc == TBS_E_BREAKDOWN && nit == 0) { result = irc; break; }
+      if (irc < 0 && irc != TBS_E_BREAKDOWN) return irc;
+      HIPCHK(launch_add_f32_to_f64(u_next, d32, c->N, c->st));
+      ++sweeps;
+    }
+    st.iters = total;
+    st.sweeps = sweeps;
+  }
+  st.status = result;
+  if (stats) *stats = st;
+  return result;
+}

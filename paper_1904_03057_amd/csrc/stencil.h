@@ -1,0 +1,37 @@
+// Launchers of the stencil tile engine and the vector/reduction kernels (host-callable).
+#pragma once
+#include "common.h"
+
+#ifndef STENCIL_TY
+#define STENCIL_TY 16
+#endif
+
+namespace tbs {
+
+constexpr int kTileX = 64;
+constexpr int kTileY = STENCIL_TY;
+
+// stencil.hip
+hipError_t launch_apply(const StencilArgs& a, int n, int bc, int in_dt, int out_dt, hipStream_t st);
+hipError_t launch_rhs(const StencilArgs& a, int n, int bc, int dt, hipStream_t st);
+hipError_t launch_cg1(const StencilArgs& a, int n, int bc, int dt, hipStream_t st);
+hipError_t launch_resid(const StencilArgs& a, int n, int bc, int r_dt, hipStream_t st);
+
+// vector.hip
+constexpr int kVecBlocks = 2048;   // grid of the elementwise kernels (= partial sums they write)
+hipError_t launch_cg2(void* r, const void* q, int64_t n, int dt, double* part, const Scalars* s, hipStream_t st);
+hipError_t launch_sub_norm(void* r, const void* b, const void* q, int64_t n, int dt, double* p0, double* p1,
+                           hipStream_t st);
+hipError_t launch_flush(void* x, const void* p0, const void* p1, int64_t n, int dt, const Scalars* s, hipStream_t st);
+hipError_t launch_dot(const void* a, const void* b, int64_t n, int dt, double* part, hipStream_t st);
+hipError_t launch_convert(const void* src, int sdt, void* dst, int ddt, int64_t n, hipStream_t st);
+hipError_t launch_add_f32_to_f64(double* x, const float* d, int64_t n, hipStream_t st);
+hipError_t launch_fill(void* x, int dt, int64_t n, hipStream_t st);  // zero fill
+hipError_t launch_guess_combine(double* x, const double* u, const float* du, int64_t n, hipStream_t st);
+
+// finalize kernels (single block, fixed-order reduction of partial sums)
+enum FinOp { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_DOT = 3, FIN_NORMS = 4, FIN_CLEAR_PENDING = 5 };
+hipError_t launch_finalize(int op, const double* p0, const double* p1, int count, Scalars* s, double rtol,
+                           hipStream_t st);
+
+}  // namespace tbs

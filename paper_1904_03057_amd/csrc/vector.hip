@@ -1,0 +1,291 @@
+// Elementwise CG updates, conversions and the fixed-order reductions (gfx950).
+//
+// Reductions are two-stage and deterministic: every kernel block writes one FP64 partial sum
+// (per-thread sums over a fixed grid-stride sequence, then a fixed butterfly over the wave and
+// a fixed combine over the block), and a single-block finalize kernel adds the partials in a
+// fixed order.  No floating-point atomics are used, so results are bitwise reproducible.
+#include "common.h"
+#include "stencil.h"
+
+namespace tbs {
+
+template <typename T>
+__device__ __forceinline__ double block_sum_write(double v, double* part) {
+  __shared__ double red[4];
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+    s = (red[0] + red[1]) + (red[2] + red[3]);
+    part[blockIdx.x] = s;
+  }
+  return s;
+}
+
+// r <- r - alpha q ; partial sums of r.r   (T = double or float)
+template <typename T>
+__global__ __launch_bounds__(256) void cg2_kernel(T* __restrict__ r, const T* __restrict__ q, int64_t n,
+                                                  double* part, const Scalars* s) {
+  if (s->done) return;
+  const T alpha = (T)s->alpha;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    const T v = r[i] - alpha * q[i];
+    r[i] = v;
+    acc += (double)v * (double)v;
+  }
+  block_sum_write<T>(acc, part);
+}
+
+// float specialisation with 4-wide accesses (arrays are 256-byte aligned)
+template <>
+__global__ __launch_bounds__(256) void cg2_kernel<float>(float* __restrict__ r, const float* __restrict__ q, int64_t n,
+                                                         double* part, const Scalars* s) {
+  if (s->done) return;
+  const float alpha = (float)s->alpha;
+  const int64_t n4 = n >> 2;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  float4* r4 = (float4*)r;
+  const float4* q4 = (const float4*)q;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n4; i += stride) {
+    float4 a = r4[i];
+    const float4 b = q4[i];
+    a.x -= alpha * b.x; a.y -= alpha * b.y; a.z -= alpha * b.z; a.w -= alpha * b.w;
+    r4[i] = a;
+    acc += ((double)a.x * a.x + (double)a.y * a.y) + ((double)a.z * a.z + (double)a.w * a.w);
+  }
+  if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
+    const int64_t i = (n4 << 2) + threadIdx.x;
+    const float v = r[i] - alpha * q[i];
+    r[i] = v;
+    acc += (double)v * v;
+  }
+  block_sum_write<float>(acc, part);
+}
+
+// r <- b - q ; partial sums of r.r (part0) and b.b (part1)
+template <typename T>
+__global__ __launch_bounds__(256) void sub_norm_kernel(T* __restrict__ r, const T* __restrict__ b,
+                                                       const T* __restrict__ q, int64_t n, double* p0, double* p1) {
+  __shared__ double red[2][4];
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  double a0 = 0.0, a1 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    const T bv = b[i];
+    const T v = bv - q[i];
+    r[i] = v;
+    a0 += (double)v * (double)v;
+    a1 += (double)bv * (double)bv;
+  }
+  a0 = wave_sum(a0);
+  a1 = wave_sum(a1);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (lane == 0) { red[0][wave] = a0; red[1][wave] = a1; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    p0[blockIdx.x] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    p1[blockIdx.x] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  }
+}
+
+// x <- x + alpha p_{nit-1}, p_{nit-1} = (nit odd ? p1 : p0), only if an update is pending
+template <typename T, typename Tp>
+__global__ __launch_bounds__(256) void flush_kernel(T* __restrict__ x, const Tp* __restrict__ p0,
+                                                    const Tp* __restrict__ p1, int64_t n, const Scalars* s) {
+  if (!s->pending) return;
+  const T alpha = (T)s->alpha;
+  const Tp* p = (s->nit & 1) ? p1 : p0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
+    x[i] += alpha * Io<Tp>::template ld<T>(p, i);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void dot_kernel(const T* __restrict__ a, const T* __restrict__ b, int64_t n,
+                                                  double* part) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) acc += (double)a[i] * (double)b[i];
+  block_sum_write<T>(acc, part);
+}
+
+template <typename Ts, typename Td>
+__global__ __launch_bounds__(256) void convert_kernel(const void* __restrict__ src, void* __restrict__ dst, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    if (sizeof(Td) == 2) {
+      // to bf16: round the fp32 value (an f64 source is first rounded to fp32)
+      const float v = Io<Ts>::template ld<float>(src, i);
+      ((uint16_t*)dst)[i] = f32_to_bf16(v);
+    } else {
+      using Tc = typename std::conditional<sizeof(Td) == 8, double, float>::type;
+      Io<Td>::template st<Tc>(dst, i, Io<Ts>::template ld<Tc>(src, i));
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void add_f32_to_f64_kernel(double* __restrict__ x, const float* __restrict__ d, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) x[i] += (double)d[i];
+}
+
+__global__ __launch_bounds__(256) void guess_combine_kernel(double* __restrict__ x, const double* __restrict__ u,
+                                                            const float* __restrict__ du, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) x[i] = u[i] + (double)du[i];
+}
+
+__global__ __launch_bounds__(256) void fill_kernel(uint32_t* __restrict__ x, int64_t nwords) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nwords; i += stride) x[i] = 0u;
+}
+
+__global__ __launch_bounds__(1024) void finalize_kernel(int op, const double* __restrict__ p0,
+                                                        const double* __restrict__ p1, int count, Scalars* s,
+                                                        double rtol) {
+  __shared__ double r0[1024], r1[1024];
+  if (op == FIN_CLEAR_PENDING) {
+    if (threadIdx.x == 0) s->pending = 0;
+    return;
+  }
+  if ((op == FIN_ALPHA || op == FIN_BETA) && s->done) return;
+  double a0 = 0.0, a1 = 0.0;
+  for (int i = threadIdx.x; i < count; i += 1024) {
+    a0 += p0[i];
+    if (p1) a1 += p1[i];
+  }
+  r0[threadIdx.x] = a0;
+  r1[threadIdx.x] = a1;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      r0[threadIdx.x] += r0[threadIdx.x + w];
+      r1[threadIdx.x] += r1[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double v0 = r0[0], v1 = r1[0];
+  switch (op) {
+    case FIN_INIT: {
+      s->rr = v0; s->rr0 = v0; s->bb = v1; s->tol2 = rtol * rtol * v1;
+      s->nit = 0; s->status = 0; s->pending = 0; s->alpha = 0.0; s->beta = 0.0;
+      int done = (v1 == 0.0) || (v0 <= s->tol2);
+      if (!isfinite(v0) || !isfinite(v1)) { s->status = -4; done = 1; }
+      s->done = done;
+      break;
+    }
+    case FIN_ALPHA: {
+      s->pending = 0;
+      s->pq = v0;
+      if (!(v0 > 0.0) || !isfinite(v0)) { s->status = -4; s->done = 1; break; }
+      s->alpha = s->rr / v0;
+      break;
+    }
+    case FIN_BETA: {
+      if (!isfinite(v0)) { s->status = -4; s->done = 1; break; }
+      s->beta = v0 / s->rr;
+      s->rr = v0;
+      s->nit += 1;
+      s->pending = 1;
+      if (v0 <= s->tol2) s->done = 1;
+      break;
+    }
+    case FIN_DOT: s->out = v0; break;
+    case FIN_NORMS: s->out = v0; s->out2 = v1; break;
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+
+static inline int vec_blocks(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > kVecBlocks) b = kVecBlocks;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+hipError_t launch_cg2(void* r, const void* q, int64_t n, int dt, double* part, const Scalars* s, hipStream_t st) {
+  // fixed grid so that the number of partial sums is always kVecBlocks
+  if (dt == 0)
+    hipLaunchKernelGGL(cg2_kernel<double>, dim3(kVecBlocks), dim3(256), 0, st, (double*)r, (const double*)q, n, part, s);
+  else
+    hipLaunchKernelGGL(cg2_kernel<float>, dim3(kVecBlocks), dim3(256), 0, st, (float*)r, (const float*)q, n, part, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_sub_norm(void* r, const void* b, const void* q, int64_t n, int dt, double* p0, double* p1,
+                           hipStream_t st) {
+  if (dt == 0)
+    hipLaunchKernelGGL(sub_norm_kernel<double>, dim3(kVecBlocks), dim3(256), 0, st, (double*)r, (const double*)b,
+                       (const double*)q, n, p0, p1);
+  else
+    hipLaunchKernelGGL(sub_norm_kernel<float>, dim3(kVecBlocks), dim3(256), 0, st, (float*)r, (const float*)b,
+                       (const float*)q, n, p0, p1);
+  return hipGetLastError();
+}
+
+hipError_t launch_flush(void* x, const void* p0, const void* p1, int64_t n, int dt, const Scalars* s, hipStream_t st) {
+  const int b = vec_blocks(n);
+  if (dt == 0)
+    hipLaunchKernelGGL((flush_kernel<double, double>), dim3(b), dim3(256), 0, st, (double*)x, (const double*)p0,
+                       (const double*)p1, n, s);
+  else if (dt == 1)
+    hipLaunchKernelGGL((flush_kernel<float, float>), dim3(b), dim3(256), 0, st, (float*)x, (const float*)p0,
+                       (const float*)p1, n, s);
+  else
+    hipLaunchKernelGGL((flush_kernel<float, uint16_t>), dim3(b), dim3(256), 0, st, (float*)x, (const uint16_t*)p0,
+                       (const uint16_t*)p1, n, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot(const void* a, const void* b, int64_t n, int dt, double* part, hipStream_t st) {
+  if (dt == 0)
+    hipLaunchKernelGGL(dot_kernel<double>, dim3(kVecBlocks), dim3(256), 0, st, (const double*)a, (const double*)b, n, part);
+  else
+    hipLaunchKernelGGL(dot_kernel<float>, dim3(kVecBlocks), dim3(256), 0, st, (const float*)a, (const float*)b, n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_convert(const void* src, int sdt, void* dst, int ddt, int64_t n, hipStream_t st) {
+  const int b = vec_blocks(n);
+#define CONV(S, D) hipLaunchKernelGGL((convert_kernel<S, D>), dim3(b), dim3(256), 0, st, src, dst, n)
+  if (sdt == 0 && ddt == 1) CONV(double, float);
+  else if (sdt == 0 && ddt == 2) CONV(double, uint16_t);
+  else if (sdt == 1 && ddt == 0) CONV(float, double);
+  else if (sdt == 1 && ddt == 2) CONV(float, uint16_t);
+  else if (sdt == 2 && ddt == 1) CONV(uint16_t, float);
+  else if (sdt == 2 && ddt == 0) CONV(uint16_t, double);
+  else return hipErrorInvalidValue;
+#undef CONV
+  return hipGetLastError();
+}
+
+hipError_t launch_add_f32_to_f64(double* x, const float* d, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(add_f32_to_f64_kernel, dim3(vec_blocks(n)), dim3(256), 0, st, x, d, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_guess_combine(double* x, const double* u, const float* du, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(guess_combine_kernel, dim3(vec_blocks(n)), dim3(256), 0, st, x, u, du, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(void* x, int dt, int64_t n, hipStream_t st) {
+  const int64_t bytes = n * (dt == 0 ? 8 : (dt == 1 ? 4 : 2));
+  const int64_t words = (bytes + 3) / 4;
+  hipLaunchKernelGGL(fill_kernel, dim3(vec_blocks(words)), dim3(256), 0, st, (uint32_t*)x, words);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(int op, const double* p0, const double* p1, int count, Scalars* s, double rtol,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, st, op, p0, p1, count, s, rtol);
+  return hipGetLastError();
+}
+
+}  // namespace tbs

@@ -1,0 +1,79 @@
+"""Host-side checks of the C ABI (no GPU): the library loads, exports every declared symbol, and
+rejects invalid arguments before any HIP call."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1904_03057_amd as tbs
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "tbs.h")
+
+
+def declared_symbols():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(tbs_[a-z0-9_]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    syms = declared_symbols()
+    assert len(syms) >= 20
+    lib = tbs.lib()
+    for s in syms:
+        assert hasattr(lib, s), s
+    assert set(syms) == set(tbs.EXPORTS)
+
+
+def _setup(grid=(16, 16, 16), n=3, h=(0.1, 0.1, 0.1), tau=1e-3, bc=tbs.DIRICHLET):
+    p = ctypes.c_void_p()
+    rc = tbs.lib().tbs_setup(ctypes.byref(p), (ctypes.c_int64 * 3)(*grid), n, (ctypes.c_double * 3)(*h), tau, bc, None)
+    return rc, p
+
+
+@pytest.mark.parametrize("kw", [dict(n=0), dict(n=6), dict(tau=0.0), dict(tau=-1.0), dict(h=(0.1, 0.0, 0.1)),
+                                dict(grid=(6, 16, 16)), dict(bc=7), dict(grid=(16, 16, 2), n=1),
+                                dict(tau=float("nan"))])
+def test_setup_rejects_bad_arguments(kw):
+    rc, p = _setup(**kw)
+    assert rc == tbs.E_INVAL and not p
+
+
+def test_valid_setup_and_workspace_sizes_without_gpu():
+    rc, p = _setup(grid=(33, 17, 9), n=2)
+    assert rc == tbs.OK
+    lib = tbs.lib()
+    base = lib.tbs_workspace_bytes(p, -1)
+    N = 33 * 17 * 9
+    assert base > 0
+    assert lib.tbs_workspace_bytes(p, tbs.PREC_FP64) >= base + 5 * N * 8
+    assert lib.tbs_workspace_bytes(p, tbs.PREC_MIXED) >= base + N * 8 + 5 * N * 4
+    assert lib.tbs_workspace_bytes(p, 9) == 0
+    m = (ctypes.c_double * 3)()
+    s = (ctypes.c_double * 3)()
+    assert lib.tbs_taps(p, m, s) == tbs.OK
+    # the library's own FP64 taps equal the exact rationals (n = 2: 11/20, 13/60, 1/120 ; 1, -1/3, -1/6)
+    assert list(m) == pytest.approx([11 / 20, 13 / 60, 1 / 120], abs=1e-15)
+    assert list(s) == pytest.approx([1.0, -1 / 3, -1 / 6], abs=1e-15)
+    lib.tbs_destroy(p)
+
+
+def test_calls_validate_pointers_before_hip():
+    rc, p = _setup()
+    lib = tbs.lib()
+    aligned = ctypes.c_void_p(1 << 20)      # never dereferenced: validation fails first
+    misaligned = ctypes.c_void_p((1 << 20) + 8)
+    assert lib.tbs_apply(p, None, tbs.F64, aligned, tbs.F64) == tbs.E_INVAL
+    assert lib.tbs_apply(p, misaligned, tbs.F64, aligned, tbs.F64) == tbs.E_INVAL
+    assert lib.tbs_apply(p, aligned, tbs.F64, aligned, tbs.F64) == tbs.E_INVAL          # aliasing
+    assert lib.tbs_apply(p, aligned, tbs.F64, ctypes.c_void_p(1 << 21), tbs.BF16) == tbs.E_INVAL  # bad dtype pair
+    assert lib.tbs_rhs(p, aligned, None, ctypes.c_void_p(1 << 21), tbs.BF16) == tbs.E_INVAL
+    assert lib.tbs_cg_step(p, 3, None, None) == tbs.E_STATE
+    assert lib.tbs_timestep(p, aligned, None, ctypes.c_void_p(1 << 21), 9, 1e-8, 10, None, None) == tbs.E_INVAL
+    # valid pointers but no workspace bound -> NOMEM before any HIP call
+    assert lib.tbs_timestep(p, aligned, None, ctypes.c_void_p(1 << 21), tbs.PREC_FP64, 1e-8, 10, None, None) == tbs.E_NOMEM
+    assert lib.tbs_bind_workspace(p, misaligned, 1 << 30) == tbs.E_INVAL
+    assert lib.tbs_bind_workspace(p, aligned, 16) == tbs.E_NOMEM
+    assert lib.tbs_strerror(tbs.E_BREAKDOWN).startswith(b"CG breakdown")
+    lib.tbs_destroy(p)
