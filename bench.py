@@ -1,0 +1,281 @@
+"""Benchmark of the tensor B-spline implicit heat step on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload heat928] [--no-cpu-baseline]
+
+A step is one implicit Euler step of the whole hot path on the 928^3 cubic Dirichlet workload
+(~0.8e9 DoF): right-hand side, initial guess (network guess with FP64 fallback test when
+trained weights are present, else u^k), FP64-refined FP32 CG to a relative residual of 1e-8.
+value = DoF advanced per second (GDoF/s of implicit stepping, inputs resident in HBM).
+Also reported: operator-apply throughput (GDoF/s) in FP64, FP32 and bf16->FP32, seconds per
+step of plain FP64 CG and of the refined solver with and without the learned guess, the
+roofline of the dominant kernel from HIP events recorded by the library on its own stream,
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GDoF/s of (M+τΣK)u apply; s per implicit step at 0.8B DoF, learned vs plain CG"
+HBM_PEAK_GBS = 8000.0
+WEIGHTS = os.path.join(ROOT, "paper_1904_03057_amd", "weights", "guess_net_128.f32")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="heat928")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="only the timed steps (for profiling runs)")
+    ap.add_argument("--probe", default=None,
+                    help="run one kernel kind --steps times for counter collection instead of the benchmark: "
+                         "apply_f64 | apply_f32 | apply_bf16 | copy (f64->f32 conversion, the traffic calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (the design notes "
+              "describe how the z-slab decomposition would shard); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    if args.probe:
+        probe(args)
+        return
+
+    import numpy as np
+    import torch
+
+    import paper_1904_03057_amd as tbs
+    import workloads
+
+    w = {"heat928": workloads.HEAT_928_DIRICHLET, "heat256": workloads.HEAT_256_DIRICHLET,
+         "heat512": workloads.HEAT_512_EVAL}[args.workload]
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    N = w.grid[0] * w.grid[1] * w.grid[2]
+    shape = w.grid[::-1]
+    log("workload %s grid %s n=%d tau=%g rtol=%g" % (w.name, w.grid, w.degree, w.tau, w.rtol))
+
+    with torch.cuda.stream(stream):
+        params = workloads.initial_field_gaussians(w)
+        u0 = workloads.gaussian_sum(w.grid, w.bc, w.h, params, xp=torch, device="cuda", dtype=torch.float64)
+        ua, ub = u0.clone(), torch.empty_like(u0)
+        ctx = tbs.Context(w.grid, w.degree, w.h, w.tau, w.bc, stream=stream)
+        # poll convergence after every CG iteration: no launch ever runs past convergence, so the
+        # profiler's per-launch averages and rocprofv3's agree (one 8-byte read per ~ms iteration)
+        ctx.set_opts(poll_every=1)
+        ctx.ensure_workspace(tbs.PREC_MIXED)
+    net = None
+    if os.path.exists(WEIGHTS):
+        net = tbs.Net(stream=stream)
+        net.set_weights(np.fromfile(WEIGHTS, dtype=np.float32))
+        net.ensure_workspace(w.grid, 1, False)
+    torch.cuda.synchronize()
+
+    def step(prec, use_net):
+        nonlocal ua, ub
+        st = ctx.timestep(ua, None, ub, prec, w.rtol, 5000, net if use_net else None)
+        ua, ub = ub, ua
+        return st
+
+    log("warmup %d" % args.warmup)
+    for _ in range(args.warmup):
+        step(tbs.PREC_MIXED, net is not None)
+    torch.cuda.synchronize()
+    ua.copy_(u0)
+    torch.cuda.synchronize()
+
+    ctx.prof_enable(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    stats = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for i in range(args.steps):
+        stats.append(step(tbs.PREC_MIXED, net is not None))
+        log("step %d: iters %d sweeps %d rel_res %.3e learned %d" % (
+            i, stats[-1]["iters"], stats[-1]["sweeps"], stats[-1]["rel_res_fp64"], stats[-1]["used_learned_guess"]))
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = e0.elapsed_time(e1)
+    prof = ctx.prof_read()
+    ctx.prof_enable(False)
+    s_step = ms_total / 1e3 / args.steps
+    value = N / s_step / 1e9
+
+    # dominant kernel of the timed region: the largest total time among the profiled kinds
+    dom = max(prof.items(), key=lambda kv: kv[1][0])
+    dname, (dms, dbytes, dcount) = dom
+    achieved = dbytes / (dms / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dname,
+                "avg_launch_ms": round(dms / dcount, 4), "launches": dcount,
+                "algorithmic_bytes_per_launch": round(dbytes / dcount)}
+
+    out = {
+        "metric": METRIC, "value": round(value, 4), "unit": "GDoF/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_total / args.steps, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": w.name, "grid": list(w.grid), "degree": w.degree, "bc": w.bc, "tau": w.tau,
+                   "rtol": w.rtol, "solver": "fp64-refined fp32 CG" + (" + learned guess" if net else ""),
+                   "global_batch": 1, "parallelism": "none"},
+        "wall_s_timed": round(wall, 3),
+        "iters_per_step": [s["iters"] for s in stats], "sweeps_per_step": [s["sweeps"] for s in stats],
+        "rel_res_fp64": max(s["rel_res_fp64"] for s in stats),
+        "roofline": roofline,
+        "kernels": {k: {"ms": round(v[0], 3), "GB/s": round(v[1] / (v[0] / 1e3) / 1e9, 1), "launches": v[2]}
+                    for k, v in prof.items()},
+    }
+
+    if not args.no_extras:
+        out.update(extras(ctx, tbs, torch, w, u0, stream, net, N))
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, params, out.get("s_per_step", {}))
+    print(json.dumps(out), flush=True)
+
+
+def probe(args):
+    """One kernel kind, --steps launches on the 928^3 field (for rocprofv3 counter passes)."""
+    import torch
+
+    import paper_1904_03057_amd as tbs
+    import workloads
+
+    w = workloads.HEAT_928_DIRICHLET
+    torch.cuda.set_device(0)
+    N = w.grid[0] * w.grid[1] * w.grid[2]
+    u = workloads.gaussian_sum(w.grid, w.bc, w.h, workloads.initial_field_gaussians(w), xp=torch,
+                               device="cuda", dtype=torch.float64)
+    ctx = tbs.Context(w.grid, w.degree, w.h, w.tau, w.bc)
+    ctx.ensure_workspace(-1)
+    kind = args.probe
+    if kind == "apply_f64":
+        src, dst = u, torch.empty_like(u)
+        run = lambda: ctx.apply(src, dst)
+        nbytes = 16 * N
+    elif kind == "apply_f32":
+        src = u.to(torch.float32)
+        dst = torch.empty_like(src)
+        run = lambda: ctx.apply(src, dst)
+        nbytes = 8 * N
+    elif kind == "apply_bf16":
+        src = u.to(torch.bfloat16)
+        dst = torch.empty(u.shape, dtype=torch.float32, device="cuda")
+        run = lambda: ctx.apply(src, dst)
+        nbytes = 6 * N
+    elif kind == "copy":
+        dst = torch.empty(u.shape, dtype=torch.float32, device="cuda")
+        run = lambda: ctx.convert(u, dst)
+        nbytes = 12 * N
+    else:
+        raise SystemExit("unknown probe " + kind)
+    torch.cuda.synchronize()
+    ctx.prof_enable(True)
+    for i in range(args.steps):
+        run()
+        log("probe %s launch %d" % (kind, i))
+    torch.cuda.synchronize()
+    p = ctx.prof_read()
+    ms = sum(v[0] for v in p.values())
+    print(json.dumps({"probe": kind, "launches": args.steps, "algorithmic_bytes_per_launch": nbytes,
+                      "avg_ms": (ms / args.steps) if ms else None}), flush=True)
+
+
+def extras(ctx, tbs, torch, w, u0, stream, net, N):
+    """Apply throughput per dtype and seconds per step of the other solver variants."""
+    res = {}
+    with torch.cuda.stream(stream):
+        y64 = torch.empty_like(u0)
+        u32 = u0.to(torch.float32)
+        y32 = torch.empty_like(u32)
+        u16 = u0.to(torch.bfloat16)
+    torch.cuda.synchronize()
+    gd = {}
+    for name, u, y in (("f64", u0, y64), ("f32", u32, y32), ("bf16_to_f32", u16, y32)):
+        for _ in range(2):
+            ctx.apply(u, y)
+        torch.cuda.synchronize()
+        ctx.prof_enable(True)
+        reps = 10
+        for _ in range(reps):
+            ctx.apply(u, y)
+        p = ctx.prof_read()
+        ctx.prof_enable(False)
+        ms, by, cnt = list(p.values())[0]
+        gd[name] = {"GDoF/s": round(N / (ms / cnt / 1e3) / 1e9, 1), "GB/s": round(by / (ms / 1e3) / 1e9, 1),
+                    "frac_hbm": round(by / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "ms": round(ms / cnt, 4)}
+        log("apply %s: %s" % (name, gd[name]))
+    res["apply"] = gd
+    del y64, u32, y32, u16
+
+    def time_steps(prec, use_net, k):
+        ua, ub = u0.clone(), torch.empty_like(u0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = []
+        for _ in range(k):
+            sts.append(ctx.timestep(ua, None, ub, prec, w.rtol, 5000, net if use_net else None))
+            ua, ub = ub, ua
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / k, sts
+
+    sp = {}
+    variants = [("plain_fp64_cg", tbs.PREC_FP64, False), ("refined_fp32", tbs.PREC_MIXED, False),
+                ("refined_fp32_bf16p", tbs.PREC_MIXED_BF16, False)]
+    if net is not None:
+        variants.append(("refined_fp32_learned", tbs.PREC_MIXED, True))
+    ctx.ensure_workspace(tbs.PREC_FP64)
+    for name, prec, use_net in variants:
+        t, sts = time_steps(prec, use_net, 2)
+        sp[name] = {"s_per_step": round(t, 4), "iters": [s["iters"] for s in sts],
+                    "rel_res_fp64": max(s["rel_res_fp64"] for s in sts),
+                    "learned_used": [s["used_learned_guess"] for s in sts]}
+        log("%s: %s" % (name, sp[name]))
+    res["s_per_step"] = sp
+    return res
+
+
+def cpu_baseline(w, params, sp):
+    """The FP64 oracle's apply on a z-slab of the same field (host, one thread), scaled to the
+    implicit-step throughput with the plain FP64 CG iteration count measured on the GPU."""
+    import numpy as np
+
+    import workloads
+    from oracle import operator as op
+
+    n = w.degree
+    planes = 12
+    z0 = w.grid[2] // 2
+    sub = (w.grid[0], w.grid[1], planes + 2 * n)
+    # the slab's own coordinates: shift the Gaussian centres instead of the nodes
+    coords_shift = np.array(params, copy=True)
+    coords_shift[:, 4] = params[:, 4] - (z0 - n) * w.h[2]
+    u = workloads.gaussian_sum(sub, w.bc, w.h, coords_shift)
+    t0 = time.perf_counter()
+    y = op.apply(u, n, w.h, w.tau, w.bc)
+    t = time.perf_counter() - t0
+    dofs = w.grid[0] * w.grid[1] * planes  # interior planes of the slab are exact
+    per_dof = t / dofs
+    it = None
+    if "plain_fp64_cg" in sp:
+        it = float(np.mean(sp["plain_fp64_cg"]["iters"]))
+    applies = (it if it is not None else 40.0) + 3  # CG applies + rhs + initial and final residual
+    step_rate = 1.0 / (per_dof * applies) / 1e9
+    return {"value": round(step_rate, 8), "unit": "GDoF/s", "cores": 1, "kind": "oracle",
+            "sample": "numpy FP64 oracle apply of a %dx%dx%d slab (%d interior planes) of the 928^3 field: "
+                      "%.1f s, %.3g s per DoF-apply; step rate = 1/(per-DoF apply time x %.1f applies per "
+                      "plain-CG step); host has %d cores, numpy elementwise ops use 1"
+                      % (sub[0], sub[1], sub[2], planes, t, per_dof, applies, os.cpu_count() or 0),
+            "apply_MDoF_per_s": round(dofs / t / 1e6, 3)}
+
+
+if __name__ == "__main__":
+    main()

@@ -193,6 +193,17 @@ int tbs_net_train_step(tbs_net* net, const float* u_k, const float* q, const flo
 int tbs_net_conv_layer(tbs_net* net, int layer, const uint16_t* x_bf16, const int64_t grid[3],
                        int periodic, float* z_out);
 
+/* ------------------------------------------------------- kernel timing --------------------- */
+/* When enabled, the library brackets each launch of its bandwidth kernels with HIP events on
+ * the context's stream and accumulates, per kernel kind, the elapsed time, the launches and the
+ * algorithmic bytes (the bytes the method must move: each input element read once, each output
+ * written once).  CG launches that found the solve already converged are not counted.
+ * Kinds: 0 apply f64, 1 apply f32, 2 apply bf16->f32, 3 rhs f64, 4 rhs f32, 5 cg-fused f64,
+ * 6 cg-fused f32, 7 cg-fused f32 with bf16 p, 8 residual f64, 9 cg-update f64, 10 cg-update f32. */
+#define TBS_PROF_KINDS 11
+int tbs_prof_enable(tbs_ctx* ctx, int on);   /* resets the counters */
+int tbs_prof_read(tbs_ctx* ctx, int kind, double* total_ms, double* total_bytes, int64_t* launches);
+
 /* ------------------------------------------------------- errors ---------------------------- */
 const char* tbs_strerror(int code);
 const char* tbs_last_error(void);

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libtbs.so")
 
 if not os.path.exists(LIB_PATH):
-    raise ImportError("libtbs.so is not built: run `python -m paper_1904_03057_amd.build` "
+    raise ImportError("libtbs.so is not built: run `python paper_1904_03057_amd/build.py` "
                       "(or __graft_entry__.build()) first")
 
 # torch ships its own HIP runtime under the same soname (libamdhip64.so.7).  Loading torch first
@@ -33,8 +33,11 @@ EXPORTS = [
     "tbs_apply", "tbs_rhs", "tbs_residual", "tbs_dot", "tbs_convert", "tbs_cg_begin", "tbs_cg_step",
     "tbs_timestep", "tbs_net_create", "tbs_net_destroy", "tbs_net_workspace_bytes", "tbs_net_bind_workspace",
     "tbs_net_set_weights", "tbs_net_get_weights", "tbs_net_set_hparams", "tbs_net_forward",
-    "tbs_net_train_step", "tbs_net_conv_layer", "tbs_strerror", "tbs_last_error",
+    "tbs_net_train_step", "tbs_net_conv_layer", "tbs_prof_enable", "tbs_prof_read", "tbs_strerror",
+    "tbs_last_error",
 ]
+PROF_KINDS = ["apply_f64", "apply_f32", "apply_bf16_f32", "rhs_f64", "rhs_f32", "cg_fused_f64", "cg_fused_f32",
+              "cg_fused_f32_bf16p", "residual_f64", "cg_update_f64", "cg_update_f32"]
 
 
 class Stats(ctypes.Structure):
@@ -82,6 +85,8 @@ _lib.tbs_net_forward.argtypes = [_vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_int,
 _lib.tbs_net_train_step.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                     ctypes.POINTER(ctypes.c_float)]
 _lib.tbs_net_conv_layer.argtypes = [_vp, ctypes.c_int, _vp, _i64p, ctypes.c_int, _vp]
+_lib.tbs_prof_enable.argtypes = [_vp, ctypes.c_int]
+_lib.tbs_prof_read.argtypes = [_vp, ctypes.c_int, _dp, _dp, ctypes.POINTER(ctypes.c_int64)]
 _lib.tbs_strerror.argtypes = [ctypes.c_int]
 _lib.tbs_strerror.restype = ctypes.c_char_p
 _lib.tbs_last_error.argtypes = []
@@ -207,6 +212,19 @@ class Context:
         rel, it = ctypes.c_double(), ctypes.c_int()
         _check(_lib.tbs_cg_step(self._h, n_iters, ctypes.byref(rel), ctypes.byref(it)), "tbs_cg_step")
         return rel.value, it.value
+
+    def prof_enable(self, on=True):
+        _check(_lib.tbs_prof_enable(self._h, int(on)), "tbs_prof_enable")
+
+    def prof_read(self):
+        """{kind: (total_ms, total_bytes, launches)} for every kind with launches."""
+        out = {}
+        for i, name in enumerate(PROF_KINDS):
+            ms, by, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+            _check(_lib.tbs_prof_read(self._h, i, ctypes.byref(ms), ctypes.byref(by), ctypes.byref(n)), "tbs_prof_read")
+            if n.value:
+                out[name] = (ms.value, by.value, n.value)
+        return out
 
     def timestep(self, u_prev, q, u_next, prec=PREC_FP64, rtol=1e-10, max_iter=1000, net=None):
         st = Stats()

@@ -1,6 +1,6 @@
 """Builds libtbs.so (HIP for gfx950) in-tree with hipcc.
 
-    python -m paper_1904_03057_amd.build [--jobs N] [--save-temps]
+    python paper_1904_03057_amd/build.py [--jobs N] [--save-temps]
 
 Every source is compiled on each call (object files go to paper_1904_03057_amd/_build/); the
 shared library is written next to this file.  No GPU is needed to build.

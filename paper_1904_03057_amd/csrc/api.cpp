@@ -9,6 +9,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "../../include/tbs.h"
 #include "common.h"
@@ -96,6 +97,13 @@ struct tbs_ctx {
   // CG session state (tbs_cg_begin / tbs_cg_step)
   int cg_active, cg_dt, cg_enq;
   void* cg_x;
+  // kernel timing (tbs_prof_enable)
+  struct ProfRec { int kind; int k; double bytes; hipEvent_t e0, e1; };
+  int prof_on;
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> prof_pool;
+  double prof_ms[TBS_PROF_KINDS], prof_bytes[TBS_PROF_KINDS];
+  int64_t prof_count[TBS_PROF_KINDS];
 };
 
 static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
@@ -203,7 +211,78 @@ extern "C" int tbs_setup(tbs_ctx** out, const int64_t grid[3], int degree, const
 extern "C" void tbs_destroy(tbs_ctx* c) {
   if (!c) return;
   if (c->host_scal) (void)hipHostFree(c->host_scal);
+  for (auto& r : c->prof_pending) { (void)hipEventDestroy(r.e0); (void)hipEventDestroy(r.e1); }
+  for (auto e : c->prof_pool) (void)hipEventDestroy(e);
   delete c;
+}
+
+// ------------------------------------------------------------------------------------------
+// kernel timing: events around launches on the context stream
+
+static hipEvent_t prof_event(tbs_ctx* c) {
+  if (!c->prof_pool.empty()) {
+    hipEvent_t e = c->prof_pool.back();
+    c->prof_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+// Opens a record (kind, CG iteration index k or -1, algorithmic bytes); returns its slot or -1.
+static int prof_begin(tbs_ctx* c, int kind, int k, double bytes) {
+  if (!c->prof_on) return -1;
+  tbs_ctx::ProfRec r{kind, k, bytes, prof_event(c), prof_event(c)};
+  if (!r.e0 || !r.e1) return -1;
+  (void)hipEventRecord(r.e0, c->st);
+  c->prof_pending.push_back(r);
+  return (int)c->prof_pending.size() - 1;
+}
+
+static void prof_end(tbs_ctx* c, int slot) {
+  if (slot >= 0) (void)hipEventRecord(c->prof_pending[slot].e1, c->st);
+}
+
+// Accumulates finished records (the stream must have been synchronised).  CG records with an
+// iteration index >= nit_limit belong to launches that found the solve converged: dropped.
+static void prof_collect(tbs_ctx* c, int nit_limit) {
+  for (auto& r : c->prof_pending) {
+    if (!(r.k >= 0 && r.k >= nit_limit)) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, r.e0, r.e1) == hipSuccess) {
+        c->prof_ms[r.kind] += ms;
+        c->prof_bytes[r.kind] += r.bytes;
+        c->prof_count[r.kind] += 1;
+      }
+    }
+    c->prof_pool.push_back(r.e0);
+    c->prof_pool.push_back(r.e1);
+  }
+  c->prof_pending.clear();
+}
+
+extern "C" int tbs_prof_enable(tbs_ctx* c, int on) {
+  if (!c) return set_err(TBS_E_INVAL, "null context");
+  if (!c->prof_pending.empty()) {
+    if (hipStreamSynchronize(c->st) != hipSuccess) return set_err(TBS_E_HIP, "stream sync failed");
+    prof_collect(c, 1 << 30);
+  }
+  c->prof_on = on ? 1 : 0;
+  for (int i = 0; i < TBS_PROF_KINDS; ++i) { c->prof_ms[i] = 0; c->prof_bytes[i] = 0; c->prof_count[i] = 0; }
+  return TBS_OK;
+}
+
+extern "C" int tbs_prof_read(tbs_ctx* c, int kind, double* ms, double* bytes, int64_t* launches) {
+  if (!c || kind < 0 || kind >= TBS_PROF_KINDS) return set_err(TBS_E_INVAL, "bad profiling kind");
+  if (!c->prof_pending.empty()) {
+    if (hipStreamSynchronize(c->st) != hipSuccess) return set_err(TBS_E_HIP, "stream sync failed");
+    prof_collect(c, 1 << 30);
+  }
+  if (ms) *ms = c->prof_ms[kind];
+  if (bytes) *bytes = c->prof_bytes[kind];
+  if (launches) *launches = c->prof_count[kind];
+  return TBS_OK;
 }
 
 extern "C" size_t tbs_workspace_bytes(const tbs_ctx* c, int prec) {
@@ -280,7 +359,12 @@ extern "C" int tbs_apply(tbs_ctx* c, const void* u, int in_dt, void* y, int out_
   StencilArgs a = base_args(c);
   a.in0 = u;
   a.out0 = y;
+  const double esz[3] = {8, 4, 2};
+  const int kind = (out_dt == TBS_F64 && in_dt == TBS_F64) ? 0 : (in_dt == TBS_F32 && out_dt == TBS_F32) ? 1
+                 : (in_dt == TBS_BF16 && out_dt == TBS_F32) ? 2 : -1;
+  const int ps = kind >= 0 ? prof_begin(c, kind, -1, (double)c->N * (esz[in_dt] + esz[out_dt])) : -1;
   HIPCHK(launch_apply(a, c->n, c->bc, in_dt, out_dt, c->st));
+  prof_end(c, ps);
   return TBS_OK;
 }
 
@@ -294,7 +378,10 @@ extern "C" int tbs_rhs(tbs_ctx* c, const void* u_prev, const void* q, void* b, i
   a.in0 = u_prev;
   a.in1 = q;
   a.out0 = b;
+  const double e = dt == TBS_F64 ? 8 : 4;
+  const int ps = prof_begin(c, dt == TBS_F64 ? 3 : 4, -1, (double)c->N * e * (q ? 3 : 2));
   HIPCHK(launch_rhs(a, c->n, c->bc, dt, c->st));
+  prof_end(c, ps);
   return TBS_OK;
 }
 
@@ -305,7 +392,9 @@ static int resid_async(tbs_ctx* c, const double* x, const double* b, void* r, in
   a.in0 = x;
   a.bvec = b;
   a.out0 = r;
+  const int ps = prof_begin(c, 8, -1, (double)c->N * (16 + (r ? (r_dt == TBS_F32 ? 4 : 8) : 0)));
   HIPCHK(launch_resid(a, c->n, c->bc, r_dt == TBS_F32 ? 1 : 0, c->st));
+  prof_end(c, ps);
   HIPCHK(launch_finalize(fin_op, part0(c), part1(c), c->nblocks, scal(c, slot), rtol, c->st));
   return TBS_OK;
 }
@@ -371,9 +460,16 @@ static int cg1_async(tbs_ctx* c, const CgArrays& A, int dt, int k) {
   a.io0 = A.x;
   a.scal = scal(c, SC_CG);
   a.first = (k == 0);
+  const double tc = dt == 0 ? 8 : 4, tp = dt == 0 ? 8 : (dt == 1 ? 4 : 2);
+  // first iteration: read r, write p and q; later: read r, p_old, x, write p, q, x
+  const double b1 = (double)c->N * (k == 0 ? (2 * tc + tp) : (4 * tc + 2 * tp));
+  int ps = prof_begin(c, 5 + dt, k, b1);
   HIPCHK(launch_cg1(a, c->n, c->bc, dt, c->st));
+  prof_end(c, ps);
   HIPCHK(launch_finalize(FIN_ALPHA, part0(c), nullptr, c->nblocks, scal(c, SC_CG), 0.0, c->st));
+  ps = prof_begin(c, dt == 0 ? 9 : 10, k, (double)c->N * 3 * tc);
   HIPCHK(launch_cg2(A.r, A.q, c->N, dt == 0 ? 0 : 1, part0(c), scal(c, SC_CG), c->st));
+  prof_end(c, ps);
   HIPCHK(launch_finalize(FIN_BETA, part0(c), nullptr, kVecBlocks, scal(c, SC_CG), 0.0, c->st));
   return TBS_OK;
 }
@@ -394,6 +490,7 @@ static int cg_loop(tbs_ctx* c, const CgArrays& A, int dt, int k0, int max_iter, 
     rc = read_scal(c, SC_CG, &s);
     if (rc) return rc;
     k = s.nit;
+    prof_collect(c, s.nit);
   }
   HIPCHK(launch_flush(A.x, A.p[0], A.p[1], c->N, dt, scal(c, SC_CG), c->st));
   HIPCHK(launch_finalize(FIN_CLEAR_PENDING, nullptr, nullptr, 0, scal(c, SC_CG), 0.0, c->st));

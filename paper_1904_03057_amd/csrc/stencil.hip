@@ -7,37 +7,57 @@
 //   y-pass  P = My U,            R = My V + ay Ky U
 //   z-pass  y = Mz R + az Kz P
 // which expands to (Mx My Mz + ax Kx My Mz + ay Mx Ky Mz + az Mx My Kz) u.  Symmetric taps are
-// applied to pair sums (u_{i-j} + u_{i+j}).
+// applied to pair sums (u_{i-j} + u_{i+j}), and every accumulation is an explicit FMA chain.
 //
-// Execution ("2.5-D" streaming): a 256-thread workgroup owns a 64 x TY tile of the x-y plane
-// and marches along z through its chunk.  Each input plane tile (with an n-wide halo) is staged
-// in LDS, the x-pass and y-pass run from LDS, and the z-pass is accumulated in registers into
-// the 2n+1 output planes a plane touches (ring of 2n+1 register slots, loop unrolled by 2n+1).
-// The next plane's global loads are issued before the current plane is filtered.
+// Execution ("2.5-D" streaming): a 256-thread workgroup owns a 64 x TY tile of the x-y plane and
+// marches along z through its chunk of planes.  Each input plane tile (halo n rows in y, halo HX
+// columns in x, HX = n rounded up to the 16-byte vector width) is fetched with 16-byte loads
+// one plane ahead into registers, converted/transformed and staged in LDS.  The x-pass (lanes =
+// columns) and the y-pass (a register column window per thread) run from LDS; the z-pass is
+// accumulated in registers into the 2n+1 output planes each input plane touches (a ring of 2n+1
+// register slots, loop unrolled by 2n+1 so every slot index is a compile-time constant).
 #include "common.h"
 #include "stencil.h"
 
 namespace tbs {
 
-template <int N>
-struct TapReg {
-  // taps in compute precision, kept in scalar registers
-  double m[N + 1], mx[N + 1], ays[N + 1], azs[N + 1];
-};
+template <typename T> __device__ __forceinline__ T fmad(T a, T b, T c);
+template <> __device__ __forceinline__ float fmad<float>(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+template <> __device__ __forceinline__ double fmad<double>(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-template <int N, int TY, int MODE, typename Tin, typename Tc, typename Tout, int BC>
+// VE consecutive elements (one 16-byte access for the staged input, or a single element).
+template <typename T, int VE> struct alignas(sizeof(T) * VE) VecN { T x[VE]; };
+
+template <typename Ts, typename Tc> __device__ __forceinline__ Tc to_c(Ts v) { return (Tc)v; }
+template <> __device__ __forceinline__ float to_c<uint16_t, float>(uint16_t v) { return bf16_to_f32(v); }
+template <> __device__ __forceinline__ double to_c<uint16_t, double>(uint16_t v) { return (double)bf16_to_f32(v); }
+template <typename Ts, typename Tc> __device__ __forceinline__ Ts from_c(Tc v) { return (Ts)v; }
+template <> __device__ __forceinline__ uint16_t from_c<uint16_t, float>(float v) { return f32_to_bf16(v); }
+
+template <int N, int TY, int MODE, typename Tin, typename Tc, typename Tout, int BC, bool VEC>
 __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
+  constexpr int VE = VEC ? 16 / (int)sizeof(Tin) : 1;
+  using Raw = VecN<Tin, VE>;   // staged input (u, u_prev, x, p_old)
+  using RawC = VecN<Tc, VE>;   // companion compute-precision vectors (q of RHS; r and x of CG1)
   constexpr int TX = 64;
-  constexpr int R = TY + 2 * N;      // staged rows
-  constexpr int C = TX + 2 * N;      // staged columns
-  constexpr int T = 2 * N + 1;       // taps
-  constexpr int NE = (R * C + 255) / 256;
-  constexpr int RPW = TY / 4;        // output rows per wave
+  constexpr int HX = ((N + VE - 1) / VE) * VE;   // x-halo rounded to whole vectors
+  constexpr int R = TY + 2 * N;                   // staged rows
+  constexpr int C = TX + 2 * HX;                  // staged columns
+  constexpr int CV = C / VE;                      // vectors per staged row
+  constexpr int T = 2 * N + 1;                    // taps
+  constexpr int CORE = TY * (TX / VE);            // vectors of the tile's own points
+  constexpr int HALO = R * CV - CORE;              // halo vectors
+  constexpr int NVC = (CORE + 255) / 256;          // core vectors per thread (slots 0..NVC-1)
+  constexpr int NVH = (HALO + 255) / 256;          // halo vectors per thread
+  constexpr int NV = NVC + NVH;
+  constexpr int RPW = TY / 4;                      // output rows per wave
+  constexpr int QD = (MODE == M_CG1) ? N + 1 : 1;  // depth of the centre-value ring (CG1)
   static_assert(TY % 4 == 0, "TY must be a multiple of 4");
 
   __shared__ Tc stage[R * C];
   __shared__ Tc su[R * TX];
   __shared__ Tc sv[R * TX];
+  __shared__ Tc cring[QD * TY * TX];  // p at the own points of the last n+1 planes (CG1 dot product)
   __shared__ double red[2][4];
 
   if (MODE == M_CG1 && a.scal->done) return;
@@ -47,10 +67,12 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
   const int wave = tid >> 6;
 
   const int bid = xcd_remap(blockIdx.x, a.nblocks);
-  const int tyi = bid % a.tiles_y;
-  const int rest = bid / a.tiles_y;
-  const int txi = rest % a.tiles_x;
-  const int czi = rest / a.tiles_x;
+  // logical order: x-tiles fastest, then y-tiles, then z-chunks, so the tiles an XCD runs at
+  // the same time are x- and y-neighbours whose halo cache lines meet in that XCD's L2
+  const int txi = bid % a.tiles_x;
+  const int rest = bid / a.tiles_x;
+  const int tyi = rest % a.tiles_y;
+  const int czi = rest / a.tiles_y;
   const int x0 = txi * TX, y0 = tyi * TY, z0 = czi * a.zc;
   const int zc_eff = min(a.zc, a.nz - z0);
   const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -66,16 +88,38 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
     azs[j] = (Tc)(a.t.az * a.t.s[j]);
   }
 
-  // plane-invariant staging offsets of this thread's elements
-  int off[NE];
+  // plane-invariant placement of this thread's staged vectors: core (own-point) vectors in
+  // slots 0..NVC-1, halo vectors (top/bottom rows, then left/right columns) after them
+  int off[NV], soff[NV];
   uint32_t valid = 0, own = 0;
 #pragma unroll
-  for (int e = 0; e < NE; ++e) {
-    const int idx = tid + 256 * e;
-    off[e] = 0;
-    if (idx < R * C) {
-      const int r = idx / C, c = idx - (idx / C) * C;
-      int gx = x0 - N + c, gy = y0 - N + r;
+  for (int v = 0; v < NV; ++v) {
+    int r = 0, cv = 0;
+    bool present;
+    if (v < NVC) {
+      const int idx = tid + 256 * v;
+      present = idx < CORE;
+      r = N + idx / (TX / VE);
+      cv = HX / VE + idx % (TX / VE);
+    } else {
+      int idx = tid + 256 * (v - NVC);
+      present = idx < HALO;
+      if (idx < 2 * N * CV) {
+        const int rr = idx / CV;
+        r = rr < N ? rr : rr + TY;
+        cv = idx % CV;
+      } else {
+        idx -= 2 * N * CV;
+        constexpr int SV = 2 * HX / VE;
+        r = N + idx / SV;
+        const int sc = idx % SV;
+        cv = sc < HX / VE ? sc : sc + TX / VE;
+      }
+    }
+    off[v] = 0;
+    soff[v] = present ? r * C + cv * VE : -1;
+    if (present) {
+      int gx = x0 - HX + cv * VE, gy = y0 - N + r;
       bool ok;
       if (BC == BC_PERIODIC) {
         gx %= nx; if (gx < 0) gx += nx;
@@ -85,10 +129,10 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
         ok = (gx >= 0 && gx < nx && gy >= 0 && gy < ny);
       }
       if (ok) {
-        valid |= 1u << e;
-        off[e] = gy * nx + gx;
+        valid |= 1u << v;
+        off[v] = gy * nx + gx;
       }
-      if (r >= N && r < N + TY && c >= N && c < N + TX && x0 + c - N < nx && y0 + r - N < ny) own |= 1u << e;
+      if (v < NVC && x0 + cv * VE - HX < nx && y0 + r - N < ny) own |= 1u << v;
     }
   }
 
@@ -97,9 +141,14 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
   const bool xupd = (MODE == M_CG1) && a.io0 != nullptr && !a.first && a.scal->pending;
   const Tc tauc = (Tc)a.t.tau;
 
-  Tc pre[NE];
-  // Load (and transform) input plane k into pre[]; own-point side effects for CG1.
-  auto load_plane = [&](int k) {
+  // prefetch registers: primary input vector (u / u_prev / p_old / x), secondary (q / r), x (CG1)
+  // two prefetch slots: plane k is staged from slot (k - kbeg) & 1 while plane k+1 is in flight
+  Raw pa[2][NV];
+  RawC pb[2][NV];
+  RawC px[2][NVC];
+  int pk[2] = {0, 0};  // plane index held in each prefetch slot
+
+  auto fetch = [&](int k, const int sl) {
     bool pvalid = true;
     int kk = k;
     if (BC == BC_PERIODIC) {
@@ -109,82 +158,115 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
     }
     const bool inchunk = (k >= z0 && k < z0 + zc_eff);
     const int64_t base = (int64_t)kk * plane;
+    pk[sl] = k;
 #pragma unroll
-    for (int e = 0; e < NE; ++e) {
-      Tc v = (Tc)0;
-      if (pvalid && ((valid >> e) & 1u)) {
-        const int64_t gi = base + off[e];
-        if (MODE == M_APPLY) {
-          v = Io<Tin>::template ld<Tc>(a.in0, gi);
+    for (int v = 0; v < NV; ++v) {
+#pragma unroll
+      for (int e = 0; e < VE; ++e) {
+        pa[sl][v].x[e] = (Tin)0;
+        pb[sl][v].x[e] = (Tc)0;
+        if (v < NVC) px[sl][v < NVC ? v : 0].x[e] = (Tc)0;
+      }
+      if (pvalid && ((valid >> v) & 1u)) {
+        const int64_t gi = base + off[v];
+        if (MODE == M_APPLY || MODE == M_RESID) {
+          pa[sl][v] = *(const Raw*)((const Tin*)a.in0 + gi);
         } else if (MODE == M_RHS) {
-          v = Io<Tin>::template ld<Tc>(a.in0, gi);
-          if (a.in1) v += tauc * Io<Tin>::template ld<Tc>(a.in1, gi);
-        } else if (MODE == M_CG1) {
-          const Tc r = Io<Tc>::template ld<Tc>(a.in0, gi);
-          Tc pold = (Tc)0;
-          if (!a.first) pold = Io<Tin>::template ld<Tc>(a.in1, gi);
-          v = storage_round<Tin, Tc>(r + beta * pold);
-          if (inchunk && ((own >> e) & 1u)) {
-            Io<Tin>::template st<Tc>(a.out1, gi, v);
-            if (xupd) {
-              Tc* x = (Tc*)a.io0;
-              x[gi] = x[gi] + alpha_prev * pold;
-            }
-          }
-        } else {  // M_RESID
-          v = Io<Tin>::template ld<Tc>(a.in0, gi);
+          pa[sl][v] = *(const Raw*)((const Tin*)a.in0 + gi);
+          if (a.in1) pb[sl][v] = *(const RawC*)((const Tc*)a.in1 + gi);
+        } else {  // CG1: in0 = r (Tc), in1 = p_old (Tin), io0 = x (Tc)
+          pb[sl][v] = *(const RawC*)((const Tc*)a.in0 + gi);
+          if (!a.first) pa[sl][v] = *(const Raw*)((const Tin*)a.in1 + gi);
+          if (v < NVC && xupd && inchunk && ((own >> v) & 1u))
+            px[sl][v < NVC ? v : 0] = *(const RawC*)((const Tc*)a.io0 + gi);
         }
       }
-      pre[e] = v;
+    }
+  };
+
+  // Transform the prefetched plane into LDS (and do the own-point side effects of CG1).
+  auto stage_plane = [&](const int sl) {
+    const int k = pk[sl];
+    int kk = k;
+    if (BC == BC_PERIODIC) { kk %= nz; if (kk < 0) kk += nz; }
+    const bool inchunk = (k >= z0 && k < z0 + zc_eff);
+    const int64_t base = (int64_t)kk * plane;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (soff[v] >= 0) {
+        Tc* dst = stage + soff[v];
+        if (MODE == M_APPLY || MODE == M_RESID) {
+#pragma unroll
+          for (int e = 0; e < VE; ++e) dst[e] = to_c<Tin, Tc>(pa[sl][v].x[e]);
+        } else if (MODE == M_RHS) {
+#pragma unroll
+          for (int e = 0; e < VE; ++e) dst[e] = fmad(tauc, pb[sl][v].x[e], to_c<Tin, Tc>(pa[sl][v].x[e]));
+        } else {
+          Raw pn;
+          RawC xn;
+          const bool ow = v < NVC && inchunk && ((own >> v) & 1u) && ((valid >> v) & 1u);
+#pragma unroll
+          for (int e = 0; e < VE; ++e) {
+            const Tc pold = to_c<Tin, Tc>(pa[sl][v].x[e]);
+            const Tc val = storage_round<Tin, Tc>(fmad(beta, pold, pb[sl][v].x[e]));
+            dst[e] = val;
+            pn.x[e] = from_c<Tin, Tc>(val);
+            if (v < NVC) xn.x[e] = fmad(alpha_prev, pold, px[sl][v < NVC ? v : 0].x[e]);
+          }
+          if (ow) {
+            const int64_t gi = base + off[v];
+            *(Raw*)((Tin*)a.out1 + gi) = pn;
+            if (xupd) *(RawC*)((Tc*)a.io0 + gi) = xn;
+          }
+        }
+      }
     }
   };
 
   Tc acc[T][RPW];
-  Tc cq[T][RPW];
 #pragma unroll
   for (int s = 0; s < T; ++s)
 #pragma unroll
-    for (int i = 0; i < RPW; ++i) { acc[s][i] = (Tc)0; cq[s][i] = (Tc)0; }
+    for (int i = 0; i < RPW; ++i) acc[s][i] = (Tc)0;
 
   double part0 = 0.0, part1 = 0.0;
   const int gxo = x0 + lane;
   const bool colown = gxo < nx;
 
   const int kbeg = z0 - N, kend = z0 + zc_eff + N;
-  load_plane(kbeg);
-  for (int kb = kbeg; kb < kend; kb += T) {
-#pragma unroll
-    for (int ph = 0; ph < T; ++ph) {
+  fetch(kbeg, 0);
+  if (kbeg + 1 < kend) fetch(kbeg + 1, 1);
+  // unrolled over 2T planes: ring slot (ph + d) mod T and prefetch slot ph & 1 are static
+  for (int kb = kbeg; kb < kend; kb += 2 * T) {
+#pragma clang loop unroll(full)
+    for (int ph = 0; ph < 2 * T; ++ph) {
       const int k = kb + ph;
-      if (k >= kend) break;
+      if (k < kend) {  // uniform: keeps the trip count constant so the ring indices are static
       const bool active = (BC == BC_PERIODIC) || (k >= 0 && k < nz);
-      if (active) {
-#pragma unroll
-        for (int e = 0; e < NE; ++e) {
-          const int idx = tid + 256 * e;
-          if (idx < R * C) stage[idx] = pre[e];
-        }
-      }
+      if (active) stage_plane(ph & 1);
       __syncthreads();
-      if (k + 1 < kend) load_plane(k + 1);
+      if (k + 2 < kend) fetch(k + 2, ph & 1);
       if (active) {
-        if (MODE == M_CG1) {
+        if constexpr (MODE == M_CG1) {
+          const int qs = ((k % QD) + QD) % QD;
 #pragma unroll
-          for (int i = 0; i < RPW; ++i) cq[ph][i] = stage[(wave * RPW + i + N) * C + lane + N];
+          for (int i = 0; i < RPW; ++i)
+            cring[(qs * TY + wave * RPW + i) * TX + lane] = stage[(wave * RPW + i + N) * C + lane + HX];
         }
-        // x-pass over all R staged rows (rows dealt to waves round-robin)
+        // x-pass over all R staged rows (rows dealt to the waves round-robin)
         for (int r = wave; r < R; r += 4) {
-          const Tc* row = stage + r * C + lane;
-          const Tc c0 = row[N];
-          Tc U = m[0] * c0, V = mx[0] * c0;
+          const Tc* row = stage + r * C + HX + lane;
+          const Tc c0 = row[0];
+          Tc U = m[0] * c0;
+          Tc Vv = mx[0] * c0;
 #pragma unroll
           for (int j = 1; j <= N; ++j) {
-            const Tc sm = row[N - j] + row[N + j];
-            U += m[j] * sm;
-            V += mx[j] * sm;
+            const Tc sm = row[-j] + row[j];
+            U = fmad(m[j], sm, U);
+            Vv = fmad(mx[j], sm, Vv);
           }
           su[r * TX + lane] = U;
-          sv[r * TX + lane] = V;
+          sv[r * TX + lane] = Vv;
         }
       }
       __syncthreads();
@@ -193,37 +275,44 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
 #pragma unroll
         for (int j = 0; j < RPW + 2 * N; ++j) {
           uc[j] = su[(wave * RPW + j) * TX + lane];
-          vc[j] = sv[(wave * RPW + j) * TX + lane];
+          if (MODE != M_RHS) vc[j] = sv[(wave * RPW + j) * TX + lane];
         }
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
           Tc P = m[0] * uc[i + N];
-          Tc Rr = m[0] * vc[i + N] + ays[0] * uc[i + N];
+          Tc Rr = (Tc)0;
+          if (MODE != M_RHS) Rr = fmad(ays[0], uc[i + N], m[0] * vc[i + N]);
 #pragma unroll
           for (int j = 1; j <= N; ++j) {
             const Tc pu = uc[i + N - j] + uc[i + N + j];
-            const Tc pv = vc[i + N - j] + vc[i + N + j];
-            P += m[j] * pu;
-            Rr += m[j] * pv + ays[j] * pu;
+            P = fmad(m[j], pu, P);
+            if (MODE != M_RHS) {
+              const Tc pv = vc[i + N - j] + vc[i + N + j];
+              Rr = fmad(m[j], pv, Rr);
+              Rr = fmad(ays[j], pu, Rr);
+            }
           }
-          // plane k adds to outputs k+d, d = -N..N, in ring slot (ph + d) mod T
+          // plane k adds to outputs k+d, d = -N..N, held in ring slot (ph + d) mod T
 #pragma unroll
           for (int d = -N; d <= N; ++d) {
-            const int s = (ph + d + 2 * T) % T;
+            const int s = (ph + d + 3 * T) % T;
             const int ad = d < 0 ? -d : d;
-            if (MODE == M_RHS) acc[s][i] += m[ad] * P;
-            else acc[s][i] += m[ad] * Rr + azs[ad] * P;
+            if (MODE == M_RHS) {
+              acc[s][i] = fmad(m[ad], P, acc[s][i]);
+            } else {
+              acc[s][i] = fmad(m[ad], Rr, acc[s][i]);
+              acc[s][i] = fmad(azs[ad], P, acc[s][i]);
+            }
           }
         }
       }
       // output plane o = k - N is complete
       {
-        constexpr int dummy = 0;
-        (void)dummy;
-        const int so = (ph - N + 2 * T) % T;
+        const int so = (ph - N + 3 * T) % T;
         const int o = k - N;
         if (o >= z0) {
           const int64_t obase = (int64_t)o * plane;
+          const int qo = ((o % QD) + QD) % QD;
 #pragma unroll
           for (int i = 0; i < RPW; ++i) {
             const int gy = y0 + wave * RPW + i;
@@ -234,19 +323,20 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
                 Io<Tout>::template st<Tc>(a.out0, gi, val);
               } else if (MODE == M_CG1) {
                 Io<Tout>::template st<Tc>(a.out0, gi, val);
-                part0 += (double)cq[so][i] * (double)val;
+                part0 = fma((double)cring[(qo * TY + wave * RPW + i) * TX + lane], (double)val, part0);
               } else {
                 const double b = a.bvec[gi];
                 const double r = b - (double)val;
                 if (a.out0) Io<Tout>::template st<double>(a.out0, gi, r);
-                part0 += r * r;
-                part1 += b * b;
+                part0 = fma(r, r, part0);
+                part1 = fma(b, b, part1);
               }
             }
           }
         }
 #pragma unroll
         for (int i = 0; i < RPW; ++i) acc[so][i] = (Tc)0;
+      }
       }
     }
   }
@@ -266,27 +356,50 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
 // ------------------------------------------------------------------------------------------
 // host-side launch helpers
 
-template <int N, int TY, int MODE, typename Tin, typename Tc, typename Tout>
-static hipError_t launch_bc(const StencilArgs& a, int bc, hipStream_t st) {
+// tile height per (mode, compute type): taller tiles cut the x-pass halo work of the
+// arithmetic-heavy FP32 apply; the CG and FP64 variants keep 16 rows for register room
+template <int MODE, typename Tc> constexpr int tile_y() {
+  return (MODE == M_APPLY && sizeof(Tc) == 4) ? 32 : 16;
+}
+
+template <int N, int MODE, typename Tin, typename Tc, typename Tout>
+static hipError_t launch_bc(const StencilArgs& a0, int bc, bool vec, hipStream_t st) {
+  constexpr int TY = tile_y<MODE, Tc>();
+  StencilArgs a = a0;  // geometry for this tile height
+  a.tiles_y = (a.ny + TY - 1) / TY;
+  a.nblocks = a.tiles_x * a.tiles_y * a.nchunks;
   dim3 grid(a.nblocks), block(256);
-  if (bc == BC_PERIODIC)
-    hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC_PERIODIC>), grid, block, 0, st, a);
-  else
-    hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC_DIRICHLET>), grid, block, 0, st, a);
+  if (vec) {
+    if (bc == BC_PERIODIC)
+      hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC_PERIODIC, true>), grid, block, 0, st, a);
+    else
+      hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC_DIRICHLET, true>), grid, block, 0, st, a);
+  } else {
+    if (bc == BC_PERIODIC)
+      hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC_PERIODIC, false>), grid, block, 0, st, a);
+    else
+      hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC_DIRICHLET, false>), grid, block, 0, st, a);
+  }
   return hipGetLastError();
 }
 
 template <int MODE, typename Tin, typename Tc, typename Tout>
 static hipError_t launch_n(const StencilArgs& a, int n, int bc, hipStream_t st) {
-  constexpr int TY = STENCIL_TY;
+  // 16-byte vector staging needs rows made of whole vectors: Nx divisible by the vector width
+  constexpr int ve = 16 / sizeof(Tin);
+  const bool vec = (a.nx % ve) == 0;
   switch (n) {
-    case 1: return launch_bc<1, TY, MODE, Tin, Tc, Tout>(a, bc, st);
-    case 2: return launch_bc<2, TY, MODE, Tin, Tc, Tout>(a, bc, st);
-    case 3: return launch_bc<3, TY, MODE, Tin, Tc, Tout>(a, bc, st);
-    case 4: return launch_bc<4, TY, MODE, Tin, Tc, Tout>(a, bc, st);
-    case 5: return launch_bc<5, TY, MODE, Tin, Tc, Tout>(a, bc, st);
+    case 1: return launch_bc<1, MODE, Tin, Tc, Tout>(a, bc, vec, st);
+    case 2: return launch_bc<2, MODE, Tin, Tc, Tout>(a, bc, vec, st);
+    case 3: return launch_bc<3, MODE, Tin, Tc, Tout>(a, bc, vec, st);
+    case 4: return launch_bc<4, MODE, Tin, Tc, Tout>(a, bc, vec, st);
+    case 5: return launch_bc<5, MODE, Tin, Tc, Tout>(a, bc, vec, st);
   }
   return hipErrorInvalidValue;
+}
+
+int stencil_tile_y(int mode, int compute_bytes) {
+  return (mode == M_APPLY && compute_bytes == 4) ? 32 : 16;
 }
 
 // dtype codes: 0 = f64, 1 = f32, 2 = bf16
