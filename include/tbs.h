@@ -79,6 +79,8 @@ typedef struct {
   int poll_every;          /* CG iterations enqueued between host convergence polls (default 4) */
   int zchunk;              /* z-planes per workgroup of the stencil kernels (0 = automatic); results
                               do not depend on it (each output sums its terms in the same order) */
+  int tile_order;          /* stencil tile order: 0 x-tiles fastest, 1 y-tiles fastest (no effect on results) */
+  int nt_store;            /* 1: stencil outputs use non-temporal stores (no effect on results) */
 } tbs_opts;
 
 /* ---------------------------------------------------------------- context ---------------- */
@@ -188,10 +190,15 @@ int tbs_net_forward(tbs_net* net, const void* u_k, const void* q, int dtype, flo
 int tbs_net_train_step(tbs_net* net, const float* u_k, const float* q, const float* du_target,
                        int batch, int periodic, double tau, float* loss_out);
 
-/* Raw pieces for kernel-level parity tests (F32 master weights are used as bf16):
- * forward with saved activations, and the loss gradient of the last forward_train call. */
-int tbs_net_conv_layer(tbs_net* net, int layer, const uint16_t* x_bf16, const int64_t grid[3],
-                       int periodic, float* z_out);
+/* Kernel-level probes for parity tests, on the bound workspace's grid, with the current weights
+ * rounded to bf16.  mode 0: out[voxel][C_out] = conv(x, W_layer) + b (x: bf16 [voxel][C_in]);
+ * mode 1: out[voxel][C_in] = transposed conv of g (bf16 [voxel][C_out]) with W_layer;
+ * mode 2 (training workspace): out[C_out][C_in][27] then out[C_out] = weight and bias gradients
+ * sum_v x[v + offset][ci] g[v][co] and sum_v g[v][co].  periodic selects circular padding. */
+int tbs_net_conv_layer(tbs_net* net, int layer, int mode, const uint16_t* x, const uint16_t* g,
+                       int periodic, float* out);
+/* Gradient (TBS_NET_PARAMS fp32, flat parameter order) accumulated by the last train step. */
+int tbs_net_get_grad(const tbs_net* net, float* host, size_t n);
 
 /* ------------------------------------------------------- kernel timing --------------------- */
 /* When enabled, the library brackets each launch of its bandwidth kernels with HIP events on

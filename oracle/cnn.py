@@ -14,7 +14,8 @@ GELU is the exact erf form x/2 (1 + erf(x / sqrt 2)).  Parameter count 15,169.
 Rounding points (matching the device kernels, which multiply bf16 x bf16 and accumulate in
 fp32): every tensor that enters a product is rounded to bf16 first -- the inputs x0, the
 weights, the stored activations y1..y3, and in the backward pass the output gradient and the
-pre-activation gradients dz1..dz3.  Arithmetic here is FP64 on those rounded values.
+pre-activation gradients dz1..dz3.  Biases are only added, so they stay fp32.  Arithmetic here
+is FP64 on those values.
 
 Tensors are [C, Z, Y, X]; weights [C_out, C_in, 3, 3, 3] indexed (dz, dy, dx).
 """
@@ -112,7 +113,7 @@ def forward(x0, theta, circular, keep=False, rounding=True):
     """x0 [2, Z, Y, X] -> o [1, Z, Y, X]; weights and x0 rounded to bf16, activations stored bf16.
     rounding=False runs the same network in plain FP64 (for finite-difference checks)."""
     rnd = to_bf16 if rounding else _identity
-    params = unpack(rnd(np.asarray(theta, dtype=np.float32 if rounding else np.float64)))
+    params = [(rnd(W), b) for W, b in unpack(np.asarray(theta, dtype=np.float32 if rounding else np.float64))]
     a = rnd(x0)
     acts, pre = [a], []
     for li, (W, b) in enumerate(params):
@@ -136,7 +137,7 @@ def loss_and_grad(x0, theta, target, circular, rounding=True):
     same rounded values.
     """
     rnd = to_bf16 if rounding else _identity
-    params = unpack(rnd(np.asarray(theta, dtype=np.float32 if rounding else np.float64)))
+    params = [(rnd(W), b) for W, b in unpack(np.asarray(theta, dtype=np.float32 if rounding else np.float64))]
     o, acts, pre = forward(x0, theta, circular, keep=True, rounding=rounding)
     diff = o - target
     loss = float(np.mean(diff * diff))

@@ -33,7 +33,7 @@ EXPORTS = [
     "tbs_apply", "tbs_rhs", "tbs_residual", "tbs_dot", "tbs_convert", "tbs_cg_begin", "tbs_cg_step",
     "tbs_timestep", "tbs_net_create", "tbs_net_destroy", "tbs_net_workspace_bytes", "tbs_net_bind_workspace",
     "tbs_net_set_weights", "tbs_net_get_weights", "tbs_net_set_hparams", "tbs_net_forward",
-    "tbs_net_train_step", "tbs_net_conv_layer", "tbs_prof_enable", "tbs_prof_read", "tbs_strerror",
+    "tbs_net_train_step", "tbs_net_conv_layer", "tbs_net_get_grad", "tbs_prof_enable", "tbs_prof_read", "tbs_strerror",
     "tbs_last_error",
 ]
 PROF_KINDS = ["apply_f64", "apply_f32", "apply_bf16_f32", "rhs_f64", "rhs_f32", "cg_fused_f64", "cg_fused_f32",
@@ -51,7 +51,8 @@ class Stats(ctypes.Structure):
 
 class Opts(ctypes.Structure):
     _fields_ = [("inner_rtol", ctypes.c_double), ("inner_max_iter", ctypes.c_int),
-                ("max_sweeps", ctypes.c_int), ("poll_every", ctypes.c_int), ("zchunk", ctypes.c_int)]
+                ("max_sweeps", ctypes.c_int), ("poll_every", ctypes.c_int), ("zchunk", ctypes.c_int),
+                ("tile_order", ctypes.c_int), ("nt_store", ctypes.c_int)]
 
 
 _vp, _i64p, _dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
@@ -84,7 +85,8 @@ _lib.tbs_net_set_hparams.argtypes = [_vp, ctypes.c_double, ctypes.c_double]
 _lib.tbs_net_forward.argtypes = [_vp, _vp, _vp, ctypes.c_int, _vp, ctypes.c_int, ctypes.c_double]
 _lib.tbs_net_train_step.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                     ctypes.POINTER(ctypes.c_float)]
-_lib.tbs_net_conv_layer.argtypes = [_vp, ctypes.c_int, _vp, _i64p, ctypes.c_int, _vp]
+_lib.tbs_net_conv_layer.argtypes = [_vp, ctypes.c_int, ctypes.c_int, _vp, _vp, ctypes.c_int, _vp]
+_lib.tbs_net_get_grad.argtypes = [_vp, ctypes.POINTER(ctypes.c_float), ctypes.c_size_t]
 _lib.tbs_prof_enable.argtypes = [_vp, ctypes.c_int]
 _lib.tbs_prof_read.argtypes = [_vp, ctypes.c_int, _dp, _dp, ctypes.POINTER(ctypes.c_int64)]
 _lib.tbs_strerror.argtypes = [ctypes.c_int]
@@ -179,8 +181,9 @@ class Context:
         _check(_lib.tbs_taps(self._h, m, s), "tbs_taps")
         return list(m), list(s)
 
-    def set_opts(self, inner_rtol=1e-4, inner_max_iter=500, max_sweeps=12, poll_every=4, zchunk=0):
-        o = Opts(inner_rtol, inner_max_iter, max_sweeps, poll_every, zchunk)
+    def set_opts(self, inner_rtol=1e-4, inner_max_iter=500, max_sweeps=12, poll_every=4, zchunk=0,
+                 tile_order=0, nt_store=0):
+        o = Opts(inner_rtol, inner_max_iter, max_sweeps, poll_every, zchunk, tile_order, nt_store)
         _check(_lib.tbs_set_opts(self._h, ctypes.byref(o)), "tbs_set_opts")
         if self._ws is not None and self._ws.numel() < self.workspace_bytes(-1):
             self._ws = None
@@ -298,7 +301,14 @@ class Net:
                                        ctypes.byref(loss) if want_loss else None), "tbs_net_train_step")
         return loss.value if want_loss else None
 
-    def conv_layer(self, layer, x_bf16, grid, periodic, z_out):
-        g = (ctypes.c_int64 * 3)(*grid)
-        _check(_lib.tbs_net_conv_layer(self._h, layer, _ptr(x_bf16), g, int(periodic), _ptr(z_out)),
+    def conv_layer(self, layer, mode, x, g, periodic, out):
+        """mode 0: forward pre-activation; 1: data gradient; 2: weight+bias gradient (see tbs.h)."""
+        _check(_lib.tbs_net_conv_layer(self._h, layer, mode, _ptr(x), _ptr(g), int(periodic), _ptr(out)),
                "tbs_net_conv_layer")
+
+    def get_grad(self):
+        import numpy as np
+        w = np.zeros(NET_PARAMS, dtype=np.float32)
+        _check(_lib.tbs_net_get_grad(self._h, w.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), w.size),
+               "tbs_net_get_grad")
+        return w

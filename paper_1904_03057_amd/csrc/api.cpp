@@ -167,6 +167,8 @@ static StencilArgs base_args(const tbs_ctx* c) {
   a.t = c->taps;
   a.part0 = part0(c);
   a.part1 = part1(c);
+  a.order = c->opts.tile_order;
+  a.nt_store = c->opts.nt_store;
   return a;
 }
 
@@ -204,6 +206,8 @@ extern "C" int tbs_setup(tbs_ctx** out, const int64_t grid[3], int degree, const
   c->opts.max_sweeps = 12;
   c->opts.poll_every = 4;
   c->opts.zchunk = 0;
+  c->opts.tile_order = 0;
+  c->opts.nt_store = 0;
   *out = c;
   return TBS_OK;
 }
@@ -310,10 +314,11 @@ extern "C" int tbs_set_opts(tbs_ctx* c, const tbs_opts* o) {
   if (!c) return set_err(TBS_E_INVAL, "null context");
   if (!o) {
     c->opts.inner_rtol = 1e-4; c->opts.inner_max_iter = 500; c->opts.max_sweeps = 12; c->opts.poll_every = 4;
-    c->opts.zchunk = 0;
+    c->opts.zchunk = 0; c->opts.tile_order = 0; c->opts.nt_store = 0;
   } else {
     if (!(o->inner_rtol > 0 && o->inner_rtol < 1) || o->inner_max_iter < 1 || o->max_sweeps < 1 ||
-        o->poll_every < 1 || o->zchunk < 0)
+        o->poll_every < 1 || o->zchunk < 0 || o->tile_order < 0 || o->tile_order > 1 || o->nt_store < 0 ||
+        o->nt_store > 1)
       return set_err(TBS_E_INVAL, "bad options");
     c->opts = *o;
   }

@@ -46,6 +46,8 @@ struct StencilArgs {
   double* part1;               // RESID: b.b
   const Scalars* scal;         // CG1: alpha, beta, done, pending
   int first;                   // CG1: first iteration (p = r)
+  int order;                   // tile order: 0 x-tiles fastest, 1 y-tiles fastest
+  int nt_store;                // 1: outputs written with non-temporal stores
 };
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
@@ -62,10 +64,16 @@ template <typename T> struct Io;
 template <> struct Io<double> {
   template <typename Tc> __device__ static Tc ld(const void* p, int64_t i) { return (Tc)((const double*)p)[i]; }
   template <typename Tc> __device__ static void st(void* p, int64_t i, Tc v) { ((double*)p)[i] = (double)v; }
+  template <typename Tc> __device__ static void st_nt(void* p, int64_t i, Tc v) {
+    __builtin_nontemporal_store((double)v, (double*)p + i);
+  }
 };
 template <> struct Io<float> {
   template <typename Tc> __device__ static Tc ld(const void* p, int64_t i) { return (Tc)((const float*)p)[i]; }
   template <typename Tc> __device__ static void st(void* p, int64_t i, Tc v) { ((float*)p)[i] = (float)v; }
+  template <typename Tc> __device__ static void st_nt(void* p, int64_t i, Tc v) {
+    __builtin_nontemporal_store((float)v, (float*)p + i);
+  }
 };
 template <> struct Io<uint16_t> {  // bf16 storage
   template <typename Tc> __device__ static Tc ld(const void* p, int64_t i) {
@@ -74,6 +82,7 @@ template <> struct Io<uint16_t> {  // bf16 storage
   template <typename Tc> __device__ static void st(void* p, int64_t i, Tc v) {
     ((uint16_t*)p)[i] = f32_to_bf16((float)v);
   }
+  template <typename Tc> __device__ static void st_nt(void* p, int64_t i, Tc v) { st<Tc>(p, i, v); }
 };
 
 // Round a compute value to what the storage type keeps (identity except for bf16).

@@ -1,0 +1,787 @@
+// Learned initial guess for the implicit step: a 4-layer 3x3x3 CNN (2 -> 16 -> 16 -> 16 -> 1,
+// exact-erf GELU) with bf16 operands on the gfx950 matrix cores and FP32 accumulation.  Not in
+// the paper (which warm-starts CG from a coarse-grid solution); the network predicts
+// u^{k+1} - u^k from (u^k, f) and the solver keeps its guess only if the FP64 residual drops.
+//
+// Activations are channels-last [voxel][16] bf16 (32 B per voxel); the first layer's input has
+// 2 channels, the last layer's output 1.  Every convolution is an implicit GEMM on
+// v_mfma_f32_16x16x32_bf16 computing Out^T = W^T In^T: M = 16 output channels (zero padded),
+// N = 16 voxels along x, K = 2 taps x 16 input channels per instruction (27 taps padded to 28).
+// A workgroup stages its input tile (halo 1) in LDS with 16 channels per voxel and each wave
+// accumulates 16-voxel rows.  The same kernel runs the backward data pass with flipped,
+// transposed weights.  Weight gradients are a deterministic two-stage reduction on the vector
+// ALUs (per-workgroup partial sums, then a fixed-order sum).  Optimiser: Adam on FP32 master
+// weights.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+
+#include "../../include/tbs.h"
+#include "common.h"
+#include "net.h"
+
+namespace tbs {
+namespace net {
+
+constexpr int NL = 4;
+constexpr int CIN[NL] = {2, 16, 16, 16};
+constexpr int COUT[NL] = {16, 16, 16, 1};
+constexpr int NSTEP = 14;         // MFMA K-steps: 28 taps (27 + one zero) / 2
+constexpr int PACK = NSTEP * 64 * 8;  // bf16 per packed layer
+constexpr int WG_PARTS = 6928;    // max partial-gradient row: 16*16*27 weights + 16 biases
+
+__host__ __device__ constexpr int woff(int l) {  // offset of W_l in the flat parameter vector
+  return l == 0 ? 0 : woff(l - 1) + CIN[l - 1] * COUT[l - 1] * 27 + COUT[l - 1];
+}
+__host__ __device__ constexpr int boff(int l) { return woff(l) + CIN[l] * COUT[l] * 27; }
+static_assert(woff(NL) == TBS_NET_PARAMS, "parameter count");
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad_f(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+struct Grid3 {
+  int nx, ny, nz;
+  int periodic;
+};
+
+// ------------------------------------------------------------------------------------------
+// convolution on the matrix cores
+
+enum Epi { EPI_GELU = 0, EPI_LINEAR = 1, EPI_BWD = 2, EPI_RAW = 3 };
+
+constexpr int CTX = 16, CTY = 8, CTZ = 4;             // output tile (x, y, z)
+constexpr int SX = CTX + 2, SY = CTY + 2, SZ = CTZ + 2;  // staged tile
+constexpr int SVOX = SX * SY * SZ;
+
+// in: [voxel][CIS] bf16; wpk: packed A operands [NSTEP][64 lanes][8]; out per epilogue:
+//   EPI_GELU:   zout (f32 [voxel][16], nullable) = acc + bias; yout (bf16 [voxel][16]) = GELU(z)
+//   EPI_LINEAR: fout (f32 [voxel]) = (acc[0] + bias[0]) * (*scale)          (last layer, 1 channel)
+//   EPI_BWD:    yout (bf16 [voxel][16]) = acc * GELU'(zprev[voxel][c])       (backward data)
+//   EPI_RAW:    fout (f32 [voxel][COS]) = acc (+ bias if bias != NULL)       (parity probes)
+template <int CIS, int COS, int EPI>
+__global__ __launch_bounds__(256) void conv_mfma(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
+                                                 const float* __restrict__ bias, Grid3 g,
+                                                 float* __restrict__ zout, uint16_t* __restrict__ yout,
+                                                 float* __restrict__ fout, const float* __restrict__ zprev,
+                                                 const double* __restrict__ scale) {
+  __shared__ __attribute__((aligned(16))) uint16_t st[SVOX * 16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tx = (g.nx + CTX - 1) / CTX, ty = (g.ny + CTY - 1) / CTY;
+  int b = blockIdx.x;
+  const int bx = b % tx; b /= tx;
+  const int by = b % ty;
+  const int bz = b / ty;
+  const int x0 = bx * CTX, y0 = by * CTY, z0 = bz * CTZ;
+  const int64_t plane = (int64_t)g.nx * g.ny;
+
+  // stage the input tile: 16 channels per voxel (channels >= CIS are zero)
+  for (int v = tid; v < SVOX; v += 256) {
+    const int sx = v % SX, sy = (v / SX) % SY, sz = v / (SX * SY);
+    int gx = x0 + sx - 1, gy = y0 + sy - 1, gz = z0 + sz - 1;
+    bool ok = true;
+    if (g.periodic) {
+      gx = (gx + g.nx) % g.nx; gy = (gy + g.ny) % g.ny; gz = (gz + g.nz) % g.nz;
+    } else {
+      ok = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
+    }
+    uint4 lo = make_uint4(0, 0, 0, 0), hi = make_uint4(0, 0, 0, 0);
+    if (ok) {
+      const int64_t vi = (int64_t)gz * plane + (int64_t)gy * g.nx + gx;
+      if (CIS == 16) {
+        const uint4* p = (const uint4*)(in + vi * 16);
+        lo = p[0];
+        hi = p[1];
+      } else if (CIS == 2) {
+        lo.x = *(const uint32_t*)(in + vi * 2);
+      } else {
+        lo.x = in[vi];
+      }
+    }
+    uint4* d = (uint4*)(st + v * 16);
+    d[0] = lo;
+    d[1] = hi;
+  }
+
+  // A operands (weights) for all 14 K-steps, kept in registers
+  bf16x8 wa[NSTEP];
+#pragma unroll
+  for (int s = 0; s < NSTEP; ++s) wa[s] = *(const bf16x8*)(wpk + (s * 64 + lane) * 8);
+  __syncthreads();
+
+  const int grp = lane >> 4;          // K-group of this lane: tap 2s + grp/2, channels 8(grp&1)..+7
+  const int vx = lane & 15;           // voxel (x) of this lane's B column / D column
+  const int chalf = (grp & 1) * 8;
+  // each wave: rows (y, z) of the tile, 16 voxels along x per row
+  for (int row = wave; row < CTY * CTZ; row += 4) {
+    const int ry = row % CTY, rz = row / CTY;
+    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < NSTEP; ++s) {
+      int tap = 2 * s + (grp >> 1);
+      if (tap > 26) tap = 13;  // padding tap: zero weights, any finite data (the centre)
+      const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
+      const int sv = ((rz + dz) * SY + (ry + dy)) * SX + (vx + dx);
+      const bf16x8 bv = *(const bf16x8*)(st + sv * 16 + chalf);
+      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s], bv, acc, 0, 0, 0);
+    }
+    // D layout: acc[r] = Out[channel 4*grp + r][voxel vx]
+    const int gx = x0 + vx, gy = y0 + ry, gz = z0 + rz;
+    if (gx < g.nx && gy < g.ny && gz < g.nz) {
+      const int64_t vi = (int64_t)gz * plane + (int64_t)gy * g.nx + gx;
+      const int c0 = 4 * grp;
+      if (EPI == EPI_GELU) {
+        float z[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) z[r] = acc[r] + bias[c0 + r];
+        if (zout) *(float4*)(zout + vi * 16 + c0) = make_float4(z[0], z[1], z[2], z[3]);
+        uint2 packed;
+        packed.x = (uint32_t)f32_to_bf16(gelu_f(z[0])) | ((uint32_t)f32_to_bf16(gelu_f(z[1])) << 16);
+        packed.y = (uint32_t)f32_to_bf16(gelu_f(z[2])) | ((uint32_t)f32_to_bf16(gelu_f(z[3])) << 16);
+        *(uint2*)(yout + vi * 16 + c0) = packed;
+      } else if (EPI == EPI_LINEAR) {
+        if (grp == 0) fout[vi] = (float)(((double)acc[0] + (double)bias[0]) * scale[0]);
+      } else if (EPI == EPI_BWD) {
+        const float4 zp = *(const float4*)(zprev + vi * 16 + c0);
+        uint2 packed;
+        packed.x = (uint32_t)f32_to_bf16(acc[0] * gelu_grad_f(zp.x)) |
+                   ((uint32_t)f32_to_bf16(acc[1] * gelu_grad_f(zp.y)) << 16);
+        packed.y = (uint32_t)f32_to_bf16(acc[2] * gelu_grad_f(zp.z)) |
+                   ((uint32_t)f32_to_bf16(acc[3] * gelu_grad_f(zp.w)) << 16);
+        *(uint2*)(yout + vi * 16 + c0) = packed;
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (c0 + r < COS) fout[vi * COS + c0 + r] = acc[r] + (bias ? bias[c0 + r] : 0.f);
+      }
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------
+// weight gradient: dW[co][ci][tap] = sum_v X[v + off(tap)][ci] G[v][co], dB[co] = sum_v G[v][co]
+// Each block accumulates its tiles (grid-stride over tiles) in registers, then writes one row of
+// partial sums; a second kernel adds the rows in a fixed order.  Work item = (co, ci) pair x row
+// group; tile = 16 (x) x 4 (y) x 4 (z) voxels staged as FP32 in LDS, channel-major.
+
+constexpr int WTX = 16, WTY = 4, WTZ = 4;
+constexpr int WSX = 20, WSY = WTY + 2, WSZ = WTZ + 2;  // x staged as -2..17 (16-byte aligned rows)
+
+template <int CIS, int COS>
+__global__ __launch_bounds__(256) void wgrad_partial(const uint16_t* __restrict__ xin, const uint16_t* __restrict__ gin,
+                                                     Grid3 g, float* __restrict__ part, int accumulate) {
+  constexpr int P = CIS * COS;                 // weight pairs
+  constexpr int NG = 256 / P;                  // row groups
+  constexpr int ROWS = WTY * WTZ;
+  __shared__ __attribute__((aligned(16))) float xs[CIS][WSZ][WSY][WSX];
+  __shared__ __attribute__((aligned(16))) float gs[COS][ROWS][WTX];
+  __shared__ float red[NG > 1 ? NG : 1][NG > 1 ? P : 1][28];
+  const int tid = threadIdx.x;
+  const int pair = tid % P, rg = tid / P;
+  const int co = pair / CIS, ci = pair % CIS;
+  const int tx = (g.nx + WTX - 1) / WTX, ty = (g.ny + WTY - 1) / WTY, tz = (g.nz + WTZ - 1) / WTZ;
+  const int ntiles = tx * ty * tz;
+  const int64_t plane = (int64_t)g.nx * g.ny;
+  float acc[27];
+  float accb = 0.f;
+#pragma unroll
+  for (int t = 0; t < 27; ++t) acc[t] = 0.f;
+
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int bx = tile % tx, by = (tile / tx) % ty, bz = tile / (tx * ty);
+    const int x0 = bx * WTX, y0 = by * WTY, z0 = bz * WTZ;
+    __syncthreads();
+    for (int v = tid; v < WSX * WSY * WSZ; v += 256) {
+      const int sx = v % WSX, sy = (v / WSX) % WSY, sz = v / (WSX * WSY);
+      int gx = x0 + sx - 2, gy = y0 + sy - 1, gz = z0 + sz - 1;
+      bool ok = true;
+      if (g.periodic) {
+        gx = (gx + g.nx) % g.nx; gy = (gy + g.ny) % g.ny; gz = (gz + g.nz) % g.nz;
+      } else {
+        ok = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
+      }
+      const int64_t vi = (int64_t)gz * plane + (int64_t)gy * g.nx + gx;
+#pragma unroll
+      for (int c = 0; c < CIS; ++c) xs[c][sz][sy][sx] = ok ? bf16_to_f32(xin[vi * CIS + c]) : 0.f;
+    }
+    for (int v = tid; v < ROWS * WTX; v += 256) {
+      const int vx = v % WTX, r = v / WTX;
+      const int gx = x0 + vx, gy = y0 + r % WTY, gz = z0 + r / WTY;
+      const bool ok = gx < g.nx && gy < g.ny && gz < g.nz;  // outputs outside the grid contribute 0
+      const int64_t vi = (int64_t)gz * plane + (int64_t)gy * g.nx + gx;
+#pragma unroll
+      for (int c = 0; c < COS; ++c) gs[c][r][vx] = ok ? bf16_to_f32(gin[vi * COS + c]) : 0.f;
+    }
+    __syncthreads();
+    for (int r = rg; r < ROWS; r += NG) {
+      const int ry = r % WTY, rz = r / WTY;
+      float gv[WTX];
+#pragma unroll
+      for (int q = 0; q < WTX; q += 4) {
+        const float4 t4 = *(const float4*)&gs[co][r][q];
+        gv[q] = t4.x; gv[q + 1] = t4.y; gv[q + 2] = t4.z; gv[q + 3] = t4.w;
+      }
+      if (ci == 0) {
+#pragma unroll
+        for (int q = 0; q < WTX; ++q) accb += gv[q];
+      }
+#pragma unroll
+      for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+          float xr[WSX];
+#pragma unroll
+          for (int q = 0; q < WSX; q += 4) {
+            const float4 t4 = *(const float4*)&xs[ci][rz + dz][ry + dy][q];
+            xr[q] = t4.x; xr[q + 1] = t4.y; xr[q + 2] = t4.z; xr[q + 3] = t4.w;
+          }
+#pragma unroll
+          for (int dx = 0; dx < 3; ++dx) {
+            float s = acc[dz * 9 + dy * 3 + dx];
+#pragma unroll
+            for (int q = 0; q < WTX; ++q) s = __builtin_fmaf(xr[q + dx + 1], gv[q], s);
+            acc[dz * 9 + dy * 3 + dx] = s;
+          }
+        }
+    }
+  }
+  // combine row groups in a fixed order, then one partial row per block
+  if (NG > 1) {
+#pragma unroll
+    for (int t = 0; t < 27; ++t) red[NG > 1 ? rg : 0][pair][t] = acc[t];
+    red[NG > 1 ? rg : 0][pair][27] = accb;
+    __syncthreads();
+    if (rg == 0) {
+      for (int q = 1; q < NG; ++q) {
+#pragma unroll
+        for (int t = 0; t < 27; ++t) acc[t] += red[q][pair][t];
+        accb += red[q][pair][27];
+      }
+    }
+  }
+  if (rg == 0) {
+    float* row = part + (int64_t)blockIdx.x * WG_PARTS;
+#pragma unroll
+    for (int t = 0; t < 27; ++t) {
+      const int j = (co * CIS + ci) * 27 + t;
+      row[j] = accumulate ? row[j] + acc[t] : acc[t];
+    }
+    if (ci == 0) {
+      const int j = COS * CIS * 27 + co;
+      row[j] = accumulate ? row[j] + accb : accb;
+    }
+  }
+}
+
+// grad[woff + j] (+)= sum over partial rows (fixed order, FP64)
+__global__ __launch_bounds__(256) void wgrad_reduce(const float* __restrict__ part, int rows, int count,
+                                                    float* __restrict__ grad, int accumulate) {
+  const int j = blockIdx.x * 256 + threadIdx.x;
+  if (j >= count) return;
+  double s = 0.0;
+  for (int r = 0; r < rows; ++r) s += part[(int64_t)r * WG_PARTS + j];
+  grad[j] = accumulate ? (float)((double)grad[j] + s) : (float)s;
+}
+
+// ------------------------------------------------------------------------------------------
+// inputs, loss, optimiser, weight packing
+
+// sum of squares of u (and q) into sc[0], sc[1] (fixed order: per-block partials then one block)
+template <typename T>
+__global__ __launch_bounds__(256) void sumsq_partial(const T* __restrict__ a, const T* __restrict__ b, int64_t n,
+                                                     double* part) {
+  __shared__ double red[2][4];
+  double s0 = 0, s1 = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double x = (double)a[i];
+    s0 = fma(x, x, s0);
+    if (b) { const double y = (double)b[i]; s1 = fma(y, y, s1); }
+  }
+  s0 = wave_sum(s0);
+  s1 = wave_sum(s1);
+  if ((threadIdx.x & 63) == 0) { red[0][threadIdx.x >> 6] = s0; red[1][threadIdx.x >> 6] = s1; }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]);
+    part[2 * blockIdx.x + 1] = (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]);
+  }
+}
+
+// sc[0] = 1/rms(u), sc[1] = 1/rms(q) (1 where the rms is 0), sc[2] = output scale tau*rms(u)*out_scale
+__global__ void scales_final(const double* __restrict__ part, int blocks, int64_t n, double tau, double out_scale,
+                             double* sc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s0 = 0, s1 = 0;
+  for (int i = 0; i < blocks; ++i) { s0 += part[2 * i]; s1 += part[2 * i + 1]; }
+  const double ru = sqrt(s0 / (double)n), rq = sqrt(s1 / (double)n);
+  sc[0] = ru > 0 ? 1.0 / ru : 1.0;
+  sc[1] = rq > 0 ? 1.0 / rq : 1.0;
+  sc[2] = tau * (ru > 0 ? ru : 1.0) * out_scale;
+  sc[3] = 1.0;
+}
+
+// x0[v] = (bf16(u * sc0), bf16(q * sc1)): the product is formed in FP64, rounded to fp32, then bf16
+template <typename T>
+__global__ __launch_bounds__(256) void prep_input(const T* __restrict__ u, const T* __restrict__ q, int64_t n,
+                                                  const double* __restrict__ sc, uint32_t* __restrict__ x0) {
+  const double a = sc[0], b = sc[1];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const uint32_t c0 = f32_to_bf16((float)((double)u[i] * a));
+    const uint32_t c1 = q ? f32_to_bf16((float)((double)q[i] * b)) : 0u;
+    x0[i] = c0 | (c1 << 16);
+  }
+}
+
+// loss partials and output gradient: t = du / sc2, diff = o - t, g = bf16(2 diff / total)
+__global__ __launch_bounds__(256) void mse_grad(const float* __restrict__ o, const float* __restrict__ du, int64_t n,
+                                                const double* __restrict__ sc, double inv_total,
+                                                uint16_t* __restrict__ gout, double* part) {
+  __shared__ double red[4];
+  const double s = sc[2];
+  double acc = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const double d = (double)o[i] - (double)du[i] / s;
+    acc = fma(d, d, acc);
+    gout[i] = f32_to_bf16((float)(2.0 * d * inv_total));
+  }
+  acc = wave_sum(acc);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+__global__ void loss_final(const double* __restrict__ part, int blocks, double inv_total, double* loss_acc,
+                           int accumulate) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double s = 0;
+  for (int i = 0; i < blocks; ++i) s += part[i];
+  loss_acc[0] = (accumulate ? loss_acc[0] : 0.0) + s * inv_total;
+}
+
+// Adam (Kingma & Ba 2015) on the FP32 master weights; t is the 1-based step
+__global__ __launch_bounds__(256) void adam(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v,
+                                            const float* __restrict__ g, int n, int t, float lr, float b1, float b2,
+                                            float eps) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  const float mh = mi / (1.0f - powf(b1, (float)t));
+  const float vh = vi / (1.0f - powf(b2, (float)t));
+  w[i] = w[i] - lr * mh / (sqrtf(vh) + eps);
+}
+
+// Packed A operands of layer l.  Forward: A[m][k] = W[m][ci][tap] with tap = 2s + (k >> 4),
+// ci = k & 15 (zero outside the layer's channels and for tap 27).  Backward data (flip = 1):
+// the transposed convolution's weights W'[ci][co][tap] = W[co][ci][26 - tap], M = ci, K = (tap, co).
+// Lane layout of v_mfma_f32_16x16x32_bf16 A: lane holds row (lane & 15), k = 8 (lane >> 4) + j.
+__global__ __launch_bounds__(64) void pack_weights(const float* __restrict__ w, int l, int flip,
+                                                   uint16_t* __restrict__ out, float* __restrict__ bias_out) {
+  const int lane = threadIdx.x;
+  const int ci_n = flip ? COUT[l] : CIN[l];   // K-channel count of this convolution
+  const int m_n = flip ? CIN[l] : COUT[l];    // output channels
+  const float* W = w + woff(l);
+  const int mrow = lane & 15, grp = lane >> 4;
+  for (int s = 0; s < NSTEP; ++s) {
+    const int tap = 2 * s + (grp >> 1);
+    for (int j = 0; j < 8; ++j) {
+      const int kc = (grp & 1) * 8 + j;
+      float val = 0.f;
+      if (tap < 27 && mrow < m_n && kc < ci_n) {
+        if (!flip) val = W[(mrow * CIN[l] + kc) * 27 + tap];
+        else val = W[(kc * CIN[l] + mrow) * 27 + (26 - tap)];
+      }
+      out[(s * 64 + lane) * 8 + j] = f32_to_bf16(val);
+    }
+  }
+  if (bias_out && lane < 16) bias_out[lane] = (!flip && lane < COUT[l]) ? w[boff(l) + lane] : 0.f;
+}
+
+}  // namespace net
+}  // namespace tbs
+
+// ==========================================================================================
+// host side
+
+using namespace tbs;
+using namespace tbs::net;
+
+namespace {
+
+constexpr int kPartBlocks = 1024;   // weight-gradient partial rows
+constexpr int kRedBlocks = 1024;    // blocks of the sum-of-squares / loss reductions
+
+struct NetWs {
+  // parameter block
+  float* master; float* m; float* v; float* grad;
+  uint16_t* wf;     // packed forward A operands, NL x PACK
+  uint16_t* wb;     // packed backward-data A operands, NL x PACK
+  float* bias;      // NL x 16
+  double* sc;       // scales: 1/rms u, 1/rms q, output scale; loss accumulator at sc[4]
+  double* red;      // reduction partials (2 x kRedBlocks)
+  float* part;      // weight-gradient partial rows kPartBlocks x WG_PARTS
+  // activations (per sample)
+  uint32_t* x0;     // N x 2 bf16
+  uint16_t* y[3];   // N x 16 bf16 (inference uses y[0], y[1] as ping-pong)
+  float* z[3];      // N x 16 f32 (training)
+  uint16_t* gz[2];  // N x 16 bf16 (training: gradients of pre-activations)
+  uint16_t* gout;   // N bf16 (training)
+  float* o;         // N f32 (network output / guess)
+};
+
+size_t a256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t layout(NetWs* L, char* base, int64_t N, int training) {
+  size_t o = 0;
+  auto take = [&](size_t bytes) { char* p = base ? base + o : nullptr; o += a256(bytes); return p; };
+  const size_t P = TBS_NET_PARAMS;
+  NetWs w{};
+  w.master = (float*)take(P * 4); w.m = (float*)take(P * 4); w.v = (float*)take(P * 4); w.grad = (float*)take(P * 4);
+  w.wf = (uint16_t*)take((size_t)NL * PACK * 2); w.wb = (uint16_t*)take((size_t)NL * PACK * 2);
+  w.bias = (float*)take(NL * 16 * 4);
+  w.sc = (double*)take(8 * 8);
+  w.red = (double*)take(2 * kRedBlocks * 8);
+  w.part = (float*)take(training ? (size_t)kPartBlocks * WG_PARTS * 4 : 0);
+  w.x0 = (uint32_t*)take((size_t)N * 4);
+  w.y[0] = (uint16_t*)take((size_t)N * 32);
+  w.y[1] = (uint16_t*)take((size_t)N * 32);
+  w.y[2] = (uint16_t*)take(training ? (size_t)N * 32 : 0);
+  for (int i = 0; i < 3; ++i) w.z[i] = (float*)take(training ? (size_t)N * 64 : 0);
+  for (int i = 0; i < 2; ++i) w.gz[i] = (uint16_t*)take(training ? (size_t)N * 32 : 0);
+  w.gout = (uint16_t*)take(training ? (size_t)N * 2 : 0);
+  w.o = (float*)take((size_t)N * 4);
+  if (L) *L = w;
+  return o;
+}
+
+thread_local char g_err[256];
+int err(int code, const char* msg) {
+  snprintf(g_err, sizeof(g_err), "%s", msg);
+  return code;
+}
+
+}  // namespace
+
+struct tbs_net {
+  hipStream_t st;
+  char* ws;
+  size_t ws_bytes;
+  int64_t grid[3];
+  int batch, training;
+  NetWs w;
+  int step;           // Adam step count
+  double out_scale;
+  double lr;
+  int weights_set;
+};
+
+#define NCHK(expr)                                                        \
+  do {                                                                    \
+    hipError_t e_ = (expr);                                               \
+    if (e_ != hipSuccess) return err(TBS_E_HIP, hipGetErrorString(e_));   \
+  } while (0)
+
+static bool aligned256(const void* p) { return p && ((uintptr_t)p & 255u) == 0; }
+
+extern "C" int tbs_net_create(tbs_net** out, void* stream) {
+  if (!out) return TBS_E_INVAL;
+  tbs_net* n = new (std::nothrow) tbs_net();
+  if (!n) return TBS_E_INVAL;
+  n->st = (hipStream_t)stream;
+  n->out_scale = 1.0;
+  n->lr = 1e-3;
+  *out = n;
+  return TBS_OK;
+}
+
+extern "C" void tbs_net_destroy(tbs_net* n) { delete n; }
+
+extern "C" size_t tbs_net_workspace_bytes(const int64_t grid[3], int batch, int training) {
+  if (!grid || grid[0] < 1 || grid[1] < 1 || grid[2] < 1 || batch < 1) return 0;
+  return layout(nullptr, nullptr, grid[0] * grid[1] * grid[2], training);
+}
+
+extern "C" int tbs_net_bind_workspace(tbs_net* n, const int64_t grid[3], int batch, int training, void* p,
+                                      size_t bytes) {
+  if (!n || !grid || batch < 1) return TBS_E_INVAL;
+  if (!aligned256(p)) return TBS_E_INVAL;
+  const size_t need = tbs_net_workspace_bytes(grid, batch, training);
+  if (need == 0 || bytes < need) return TBS_E_NOMEM;
+  const bool keep = n->ws && n->weights_set;
+  float host_params[TBS_NET_PARAMS];
+  float host_m[TBS_NET_PARAMS], host_v[TBS_NET_PARAMS];
+  if (keep) {
+    // carry the parameter block (weights and Adam moments) over to the new workspace
+    NCHK(hipMemcpyAsync(host_params, n->w.master, sizeof(host_params), hipMemcpyDeviceToHost, n->st));
+    NCHK(hipMemcpyAsync(host_m, n->w.m, sizeof(host_m), hipMemcpyDeviceToHost, n->st));
+    NCHK(hipMemcpyAsync(host_v, n->w.v, sizeof(host_v), hipMemcpyDeviceToHost, n->st));
+    NCHK(hipStreamSynchronize(n->st));
+  }
+  n->ws = (char*)p;
+  n->ws_bytes = bytes;
+  for (int d = 0; d < 3; ++d) n->grid[d] = grid[d];
+  n->batch = batch;
+  n->training = training;
+  layout(&n->w, n->ws, grid[0] * grid[1] * grid[2], training);
+  if (keep) {
+    NCHK(hipMemcpyAsync(n->w.master, host_params, sizeof(host_params), hipMemcpyHostToDevice, n->st));
+    NCHK(hipMemcpyAsync(n->w.m, host_m, sizeof(host_m), hipMemcpyHostToDevice, n->st));
+    NCHK(hipMemcpyAsync(n->w.v, host_v, sizeof(host_v), hipMemcpyHostToDevice, n->st));
+    for (int l = 0; l < NL; ++l) {
+      hipLaunchKernelGGL(pack_weights, dim3(1), dim3(64), 0, n->st, n->w.master, l, 0, n->w.wf + l * PACK, n->w.bias + l * 16);
+      hipLaunchKernelGGL(pack_weights, dim3(1), dim3(64), 0, n->st, n->w.master, l, 1, n->w.wb + l * PACK, nullptr);
+    }
+    NCHK(hipStreamSynchronize(n->st));
+  } else {
+    n->weights_set = 0;
+  }
+  return TBS_OK;
+}
+
+static int repack(tbs_net* n) {
+  for (int l = 0; l < NL; ++l) {
+    hipLaunchKernelGGL(pack_weights, dim3(1), dim3(64), 0, n->st, n->w.master, l, 0, n->w.wf + l * PACK, n->w.bias + l * 16);
+    hipLaunchKernelGGL(pack_weights, dim3(1), dim3(64), 0, n->st, n->w.master, l, 1, n->w.wb + l * PACK, nullptr);
+  }
+  NCHK(hipGetLastError());
+  return TBS_OK;
+}
+
+extern "C" int tbs_net_set_weights(tbs_net* n, const float* host, size_t count) {
+  if (!n || !host || count != TBS_NET_PARAMS) return TBS_E_INVAL;
+  if (!n->ws) return TBS_E_NOMEM;
+  for (size_t i = 0; i < count; ++i)
+    if (!std::isfinite(host[i])) return err(TBS_E_INVAL, "non-finite weight");
+  NCHK(hipMemcpyAsync(n->w.master, host, count * 4, hipMemcpyHostToDevice, n->st));
+  NCHK(hipMemsetAsync(n->w.m, 0, count * 4, n->st));
+  NCHK(hipMemsetAsync(n->w.v, 0, count * 4, n->st));
+  n->step = 0;
+  int rc = repack(n);
+  if (rc) return rc;
+  NCHK(hipStreamSynchronize(n->st));
+  n->weights_set = 1;
+  return TBS_OK;
+}
+
+extern "C" int tbs_net_get_weights(const tbs_net* n, float* host, size_t count) {
+  if (!n || !host || count != TBS_NET_PARAMS) return TBS_E_INVAL;
+  if (!n->ws || !n->weights_set) return TBS_E_STATE;
+  NCHK(hipMemcpyAsync(host, n->w.master, count * 4, hipMemcpyDeviceToHost, n->st));
+  NCHK(hipStreamSynchronize(n->st));
+  return TBS_OK;
+}
+
+extern "C" int tbs_net_set_hparams(tbs_net* n, double out_scale, double lr) {
+  if (!n || !(out_scale > 0) || !(lr > 0) || !std::isfinite(out_scale) || !std::isfinite(lr)) return TBS_E_INVAL;
+  n->out_scale = out_scale;
+  n->lr = lr;
+  return TBS_OK;
+}
+
+static int check_grid(const tbs_net* n, const int64_t grid[3]) {
+  if (!n->ws) return err(TBS_E_NOMEM, "no workspace bound");
+  if (!n->weights_set) return err(TBS_E_STATE, "weights not set");
+  for (int d = 0; d < 3; ++d)
+    if (grid[d] != n->grid[d]) return err(TBS_E_INVAL, "grid differs from the bound workspace");
+  return TBS_OK;
+}
+
+static int conv_blocks(const int64_t grid[3]) {
+  return (int)(((grid[0] + CTX - 1) / CTX) * ((grid[1] + CTY - 1) / CTY) * ((grid[2] + CTZ - 1) / CTZ));
+}
+
+// forward of one sample; x0 already prepared.  keep = training (store z and all y, and leave the
+// network output unscaled for the loss); otherwise the output is the guess du = o * sc[2].
+static int forward_layers(tbs_net* n, Grid3 g, int keep) {
+  const int64_t grid[3] = {g.nx, g.ny, g.nz};
+  const int nb = conv_blocks(grid);
+  NetWs& w = n->w;
+  uint16_t* y0 = keep ? w.y[0] : w.y[0];
+  uint16_t* y1 = keep ? w.y[1] : w.y[1];
+  uint16_t* y2 = keep ? w.y[2] : w.y[0];
+  hipLaunchKernelGGL((conv_mfma<2, 16, EPI_GELU>), dim3(nb), dim3(256), 0, n->st, (const uint16_t*)w.x0, w.wf,
+                     w.bias, g, keep ? w.z[0] : nullptr, y0, nullptr, nullptr, nullptr);
+  hipLaunchKernelGGL((conv_mfma<16, 16, EPI_GELU>), dim3(nb), dim3(256), 0, n->st, (const uint16_t*)y0,
+                     w.wf + PACK, w.bias + 16, g, keep ? w.z[1] : nullptr, y1, nullptr, nullptr, nullptr);
+  hipLaunchKernelGGL((conv_mfma<16, 16, EPI_GELU>), dim3(nb), dim3(256), 0, n->st, (const uint16_t*)y1,
+                     w.wf + 2 * PACK, w.bias + 32, g, keep ? w.z[2] : nullptr, y2, nullptr, nullptr, nullptr);
+  hipLaunchKernelGGL((conv_mfma<16, 1, EPI_LINEAR>), dim3(nb), dim3(256), 0, n->st, (const uint16_t*)y2,
+                     w.wf + 3 * PACK, w.bias + 48, g, nullptr, nullptr, w.o, nullptr,
+                     (const double*)(w.sc + (keep ? 3 : 2)));
+  NCHK(hipGetLastError());
+  return TBS_OK;
+}
+
+template <typename T>
+static int prepare(tbs_net* n, const T* u, const T* q, int64_t N, double tau, double out_scale) {
+  NetWs& w = n->w;
+  hipLaunchKernelGGL(sumsq_partial<T>, dim3(kRedBlocks), dim3(256), 0, n->st, u, q, N, w.red);
+  hipLaunchKernelGGL(scales_final, dim3(1), dim3(64), 0, n->st, (const double*)w.red, kRedBlocks, N, tau, out_scale,
+                     w.sc);
+  hipLaunchKernelGGL(prep_input<T>, dim3(2048), dim3(256), 0, n->st, u, q, N, (const double*)w.sc, w.x0);
+  NCHK(hipGetLastError());
+  return TBS_OK;
+}
+
+extern "C" int tbs_net_forward(tbs_net* n, const void* u, const void* q, int dtype, float* du, int periodic,
+                               double tau) {
+  if (!n || !aligned256(u) || !aligned256(du) || (q && !aligned256(q))) return TBS_E_INVAL;
+  if (dtype != TBS_F64 && dtype != TBS_F32) return TBS_E_INVAL;
+  if (!(tau > 0)) return TBS_E_INVAL;
+  int rc = check_grid(n, n->grid);
+  if (rc) return rc;
+  const int64_t N = n->grid[0] * n->grid[1] * n->grid[2];
+  Grid3 g{(int)n->grid[0], (int)n->grid[1], (int)n->grid[2], periodic ? 1 : 0};
+  rc = dtype == TBS_F64 ? prepare(n, (const double*)u, (const double*)q, N, tau, n->out_scale)
+                        : prepare(n, (const float*)u, (const float*)q, N, tau, n->out_scale);
+  if (rc) return rc;
+  rc = forward_layers(n, g, 0);
+  if (rc) return rc;
+  if (du != n->w.o) NCHK(hipMemcpyAsync(du, n->w.o, (size_t)N * 4, hipMemcpyDeviceToDevice, n->st));
+  return TBS_OK;
+}
+
+int tbs_net_guess_internal(tbs_net* n, const int64_t grid[3], int periodic, double tau, hipStream_t st,
+                           const double* u_prev, const double* q, const float** du_out) {
+  if (!n) return TBS_E_INVAL;
+  int rc = check_grid(n, grid);
+  if (rc) return rc;
+  if (n->st != st) return err(TBS_E_INVAL, "network and solver must share one stream");
+  const int64_t N = grid[0] * grid[1] * grid[2];
+  Grid3 g{(int)grid[0], (int)grid[1], (int)grid[2], periodic ? 1 : 0};
+  rc = prepare(n, u_prev, q, N, tau, n->out_scale);
+  if (rc) return rc;
+  rc = forward_layers(n, g, 0);
+  if (rc) return rc;
+  *du_out = n->w.o;
+  return TBS_OK;
+}
+
+extern "C" int tbs_net_train_step(tbs_net* n, const float* u, const float* q, const float* du_t, int batch,
+                                  int periodic, double tau, float* loss_out) {
+  if (!n || !aligned256(u) || !aligned256(du_t) || (q && !aligned256(q)) || batch < 1) return TBS_E_INVAL;
+  if (!(tau > 0)) return TBS_E_INVAL;
+  int rc = check_grid(n, n->grid);
+  if (rc) return rc;
+  if (!n->training) return err(TBS_E_STATE, "workspace bound without training buffers");
+  const int64_t N = n->grid[0] * n->grid[1] * n->grid[2];
+  Grid3 g{(int)n->grid[0], (int)n->grid[1], (int)n->grid[2], periodic ? 1 : 0};
+  NetWs& w = n->w;
+  const int nb = conv_blocks(n->grid);
+  const double inv_total = 1.0 / ((double)N * batch);
+  const int wblocks = kPartBlocks;
+  for (int b = 0; b < batch; ++b) {
+    const float* ub = u + (size_t)b * N;
+    const float* qb = q ? q + (size_t)b * N : nullptr;
+    const float* tb = du_t + (size_t)b * N;
+    rc = prepare(n, ub, qb, N, tau, n->out_scale);
+    if (rc) return rc;
+    rc = forward_layers(n, g, 1);
+    if (rc) return rc;
+    hipLaunchKernelGGL(mse_grad, dim3(kRedBlocks), dim3(256), 0, n->st, (const float*)w.o, tb, N,
+                       (const double*)w.sc, inv_total, w.gout, w.red);
+    hipLaunchKernelGGL(loss_final, dim3(1), dim3(64), 0, n->st, (const double*)w.red, kRedBlocks, inv_total,
+                       w.sc + 4, b > 0);
+    const int acc = b > 0;
+    // layer 4: dW4 = sum y3 (x) g ; dZ3 = convT(g, W4) * GELU'(z3)
+    hipLaunchKernelGGL((wgrad_partial<16, 1>), dim3(wblocks), dim3(256), 0, n->st, (const uint16_t*)w.y[2],
+                       (const uint16_t*)w.gout, g, w.part, 0);
+    hipLaunchKernelGGL(wgrad_reduce, dim3((16 * 27 + 1 + 255) / 256), dim3(256), 0, n->st, (const float*)w.part,
+                       wblocks, 16 * 27 + 1, w.grad + woff(3), acc);
+    hipLaunchKernelGGL((conv_mfma<1, 16, EPI_BWD>), dim3(nb), dim3(256), 0, n->st, (const uint16_t*)w.gout,
+                       w.wb + 3 * PACK, nullptr, g, nullptr, w.gz[0], nullptr, (const float*)w.z[2], nullptr);
+    // layer 3: dW3 = sum y2 (x) dZ3 ; dZ2 = convT(dZ3, W3) * GELU'(z2)
+    hipLaunchKernelGGL((wgrad_partial<16, 16>), dim3(wblocks), dim3(256), 0, n->st, (const uint16_t*)w.y[1],
+                       (const uint16_t*)w.gz[0], g, w.part, 0);
+    hipLaunchKernelGGL(wgrad_reduce, dim3((16 * 16 * 27 + 16 + 255) / 256), dim3(256), 0, n->st,
+                       (const float*)w.part, wblocks, 16 * 16 * 27 + 16, w.grad + woff(2), acc);
+    hipLaunchKernelGGL((conv_mfma<16, 16, EPI_BWD>), dim3(nb), dim3(256), 0, n->st, (const uint16_t*)w.gz[0],
+                       w.wb + 2 * PACK, nullptr, g, nullptr, w.gz[1], nullptr, (const float*)w.z[1], nullptr);
+    // layer 2: dW2 = sum y1 (x) dZ2 ; dZ1 = convT(dZ2, W2) * GELU'(z1)
+    hipLaunchKernelGGL((wgrad_partial<16, 16>), dim3(wblocks), dim3(256), 0, n->st, (const uint16_t*)w.y[0],
+                       (const uint16_t*)w.gz[1], g, w.part, 0);
+    hipLaunchKernelGGL(wgrad_reduce, dim3((16 * 16 * 27 + 16 + 255) / 256), dim3(256), 0, n->st,
+                       (const float*)w.part, wblocks, 16 * 16 * 27 + 16, w.grad + woff(1), acc);
+    hipLaunchKernelGGL((conv_mfma<16, 16, EPI_BWD>), dim3(nb), dim3(256), 0, n->st, (const uint16_t*)w.gz[1],
+                       w.wb + PACK, nullptr, g, nullptr, w.gz[0], nullptr, (const float*)w.z[0], nullptr);
+    // layer 1: dW1 = sum x0 (x) dZ1
+    hipLaunchKernelGGL((wgrad_partial<2, 16>), dim3(wblocks), dim3(256), 0, n->st, (const uint16_t*)w.x0,
+                       (const uint16_t*)w.gz[0], g, w.part, 0);
+    hipLaunchKernelGGL(wgrad_reduce, dim3((2 * 16 * 27 + 16 + 255) / 256), dim3(256), 0, n->st,
+                       (const float*)w.part, wblocks, 2 * 16 * 27 + 16, w.grad + woff(0), acc);
+    NCHK(hipGetLastError());
+  }
+  n->step += 1;
+  hipLaunchKernelGGL(adam, dim3((TBS_NET_PARAMS + 255) / 256), dim3(256), 0, n->st, w.master, w.m, w.v,
+                     (const float*)w.grad, TBS_NET_PARAMS, n->step, (float)n->lr, 0.9f, 0.999f, 1e-8f);
+  rc = repack(n);
+  if (rc) return rc;
+  if (loss_out) {
+    double l = 0;
+    NCHK(hipMemcpyAsync(&l, w.sc + 4, 8, hipMemcpyDeviceToHost, n->st));
+    NCHK(hipStreamSynchronize(n->st));
+    *loss_out = (float)l;
+  }
+  return TBS_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// kernel-level probes for parity tests (use the bound workspace's grid)
+
+extern "C" int tbs_net_conv_layer(tbs_net* n, int layer, int mode, const uint16_t* x, const uint16_t* gin,
+                                  int periodic, float* out) {
+  if (!n || layer < 0 || layer >= NL || mode < 0 || mode > 2 || !aligned256(out)) return TBS_E_INVAL;
+  int rc = check_grid(n, n->grid);
+  if (rc) return rc;
+  Grid3 g{(int)n->grid[0], (int)n->grid[1], (int)n->grid[2], periodic ? 1 : 0};
+  const int nb = conv_blocks(n->grid);
+  NetWs& w = n->w;
+  const int ci = CIN[layer], co = COUT[layer];
+  if (mode == 0) {  // forward pre-activation z = conv(x, W) + b, out [voxel][co]
+    if (!aligned256(x)) return TBS_E_INVAL;
+#define FWD(CI, CO) hipLaunchKernelGGL((conv_mfma<CI, CO, EPI_RAW>), dim3(nb), dim3(256), 0, n->st, x, \
+                                       w.wf + layer * PACK, w.bias + layer * 16, g, nullptr, nullptr, out, nullptr, nullptr)
+    if (ci == 2) FWD(2, 16);
+    else if (co == 16) FWD(16, 16);
+    else FWD(16, 1);
+#undef FWD
+  } else if (mode == 1) {  // data gradient dx = convT(g, W), out [voxel][ci]
+    if (!aligned256(gin)) return TBS_E_INVAL;
+#define BWD(CI, CO) hipLaunchKernelGGL((conv_mfma<CI, CO, EPI_RAW>), dim3(nb), dim3(256), 0, n->st, gin, \
+                                       w.wb + layer * PACK, nullptr, g, nullptr, nullptr, out, nullptr, nullptr)
+    if (co == 1) BWD(1, 16);
+    else if (ci == 2) BWD(16, 2);
+    else BWD(16, 16);
+#undef BWD
+  } else {  // weight gradient: out [co][ci][27] then [co] biases
+    if (!n->training) return err(TBS_E_STATE, "weight gradients need a training workspace");
+    if (!aligned256(x) || !aligned256(gin)) return TBS_E_INVAL;
+    if (ci == 2) hipLaunchKernelGGL((wgrad_partial<2, 16>), dim3(kPartBlocks), dim3(256), 0, n->st, x, gin, g, w.part, 0);
+    else if (co == 16) hipLaunchKernelGGL((wgrad_partial<16, 16>), dim3(kPartBlocks), dim3(256), 0, n->st, x, gin, g, w.part, 0);
+    else hipLaunchKernelGGL((wgrad_partial<16, 1>), dim3(kPartBlocks), dim3(256), 0, n->st, x, gin, g, w.part, 0);
+    const int cnt = ci * co * 27 + co;
+    hipLaunchKernelGGL(wgrad_reduce, dim3((cnt + 255) / 256), dim3(256), 0, n->st, (const float*)w.part,
+                       kPartBlocks, cnt, out, 0);
+  }
+  NCHK(hipGetLastError());
+  return TBS_OK;
+}
+
+// gradient of the last train step (flat parameter order) for parity tests
+extern "C" int tbs_net_get_grad(const tbs_net* n, float* host, size_t count) {
+  if (!n || !host || count != TBS_NET_PARAMS) return TBS_E_INVAL;
+  if (!n->ws || !n->training) return TBS_E_STATE;
+  NCHK(hipMemcpyAsync(host, n->w.grad, count * 4, hipMemcpyDeviceToHost, n->st));
+  NCHK(hipStreamSynchronize(n->st));
+  return TBS_OK;
+}

@@ -67,12 +67,20 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
   const int wave = tid >> 6;
 
   const int bid = xcd_remap(blockIdx.x, a.nblocks);
-  // logical order: x-tiles fastest, then y-tiles, then z-chunks, so the tiles an XCD runs at
-  // the same time are x- and y-neighbours whose halo cache lines meet in that XCD's L2
-  const int txi = bid % a.tiles_x;
-  const int rest = bid / a.tiles_x;
-  const int tyi = rest % a.tiles_y;
-  const int czi = rest / a.tiles_y;
+  // logical tile order (x- or y-tiles fastest, then the other, then z-chunks): the tiles an XCD
+  // runs at the same time are neighbours whose halo cache lines meet in that XCD's L2
+  int txi, tyi, czi;
+  if (a.order == 0) {
+    txi = bid % a.tiles_x;
+    const int rest = bid / a.tiles_x;
+    tyi = rest % a.tiles_y;
+    czi = rest / a.tiles_y;
+  } else {
+    tyi = bid % a.tiles_y;
+    const int rest = bid / a.tiles_y;
+    txi = rest % a.tiles_x;
+    czi = rest / a.tiles_x;
+  }
   const int x0 = txi * TX, y0 = tyi * TY, z0 = czi * a.zc;
   const int zc_eff = min(a.zc, a.nz - z0);
   const int nx = a.nx, ny = a.ny, nz = a.nz;
@@ -320,9 +328,11 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
               const int64_t gi = obase + (int64_t)gy * nx + gxo;
               const Tc val = acc[so][i];
               if (MODE == M_APPLY || MODE == M_RHS) {
-                Io<Tout>::template st<Tc>(a.out0, gi, val);
+                if (a.nt_store) Io<Tout>::template st_nt<Tc>(a.out0, gi, val);
+                else Io<Tout>::template st<Tc>(a.out0, gi, val);
               } else if (MODE == M_CG1) {
-                Io<Tout>::template st<Tc>(a.out0, gi, val);
+                if (a.nt_store) Io<Tout>::template st_nt<Tc>(a.out0, gi, val);
+                else Io<Tout>::template st<Tc>(a.out0, gi, val);
                 part0 = fma((double)cring[(qo * TY + wave * RPW + i) * TX + lane], (double)val, part0);
               } else {
                 const double b = a.bvec[gi];

@@ -1,0 +1,190 @@
+"""Parity of the learned-guess network kernels (bf16 matrix-core convolutions, weight gradients,
+loss, Adam) with the FP64 oracle evaluated on the same bf16-rounded values."""
+import numpy as np
+import pytest
+
+from oracle import cnn, operator as op
+from oracle.rounding import to_bf16
+from tests.gpu_util import dev, host
+from workloads import cnn_init, normal_field
+
+pytestmark = pytest.mark.gpu
+tbs = pytest.importorskip("paper_1904_03057_amd")
+torch = pytest.importorskip("torch")
+
+GRIDS = [(21, 13, 9), (16, 8, 4), (35, 17, 6)]
+
+
+def _net(grid, training=False, theta=None, seed=3):
+    n = tbs.Net()
+    n.ensure_workspace(grid, 1, training)
+    n.set_weights(cnn_init(seed) if theta is None else theta)
+    return n
+
+
+def _cl(a):
+    """[C, Z, Y, X] -> channels-last [Z, Y, X, C] bf16 device tensor (values already bf16)."""
+    return torch.from_numpy(np.ascontiguousarray(np.moveaxis(a, 0, -1))).to(torch.bfloat16).cuda().contiguous()
+
+
+def _from_cl(t):
+    return np.moveaxis(t.detach().to(torch.float64).cpu().numpy(), -1, 0)
+
+
+def _abs_conv(x, W, circular):
+    return cnn.conv3d(np.abs(x), np.abs(W), None, circular)
+
+
+@pytest.mark.parametrize("circular", [False, True])
+@pytest.mark.parametrize("gi", range(len(GRIDS)))
+@pytest.mark.parametrize("layer", [0, 1, 3])
+def test_conv_forward_matches_oracle(circular, gi, layer):
+    grid = GRIDS[gi]
+    ci, co = cnn.LAYERS[layer]
+    theta = cnn_init(7)
+    theta[cnn.N_PARAMS - 1] = 0.25
+    net = _net(grid, theta=theta)
+    W, b = cnn.unpack(to_bf16(theta))[layer]
+    b = cnn.unpack(theta.astype(np.float64))[layer][1]   # biases stay fp32
+    x = to_bf16(normal_field((ci,) + grid[::-1], 40 + layer))
+    out = torch.empty(grid[::-1] + (co,), dtype=torch.float32, device="cuda")
+    net.conv_layer(layer, 0, _cl(x), None, circular, out)
+    ref = cnn.conv3d(x, W, b, circular)
+    tol = 1e-5 * _abs_conv(x, W, circular) + 1e-6
+    assert np.all(np.abs(_from_cl(out) - ref) <= tol)
+
+
+@pytest.mark.parametrize("circular", [False, True])
+@pytest.mark.parametrize("layer", [1, 2, 3])
+def test_conv_data_grad_matches_oracle(circular, layer):
+    grid = (21, 13, 9)
+    ci, co = cnn.LAYERS[layer]
+    theta = cnn_init(8)
+    net = _net(grid, theta=theta)
+    W = cnn.unpack(to_bf16(theta))[layer][0]
+    g = to_bf16(normal_field((co,) + grid[::-1], 50 + layer))
+    out = torch.empty(grid[::-1] + (ci,), dtype=torch.float32, device="cuda")
+    net.conv_layer(layer, 1, None, _cl(g), circular, out)
+    ref = cnn.conv3d_data_grad(g, W, circular)
+    tol = 1e-5 * cnn.conv3d_data_grad(np.abs(g), np.abs(W), circular) + 1e-6
+    assert np.all(np.abs(_from_cl(out) - ref) <= tol)
+
+
+@pytest.mark.parametrize("circular", [False, True])
+@pytest.mark.parametrize("layer", [0, 1, 3])
+def test_weight_grad_matches_oracle(circular, layer):
+    grid = (35, 17, 10)
+    ci, co = cnn.LAYERS[layer]
+    net = _net(grid, training=True)
+    x = to_bf16(normal_field((ci,) + grid[::-1], 60 + layer))
+    g = to_bf16(normal_field((co,) + grid[::-1], 70 + layer))
+    out = torch.empty(co * ci * 27 + co, dtype=torch.float32, device="cuda")
+    net.conv_layer(layer, 2, _cl(x), _cl(g), circular, out)
+    dW, db = cnn.conv3d_weight_grad(x, g, circular)
+    scale = cnn.conv3d_weight_grad(np.abs(x), np.abs(g), circular)[0]
+    o = host(out)
+    assert np.all(np.abs(o[:co * ci * 27] - dW.ravel()) <= 1e-5 * scale.ravel() + 1e-6)
+    assert np.allclose(o[co * ci * 27:], db, rtol=1e-5, atol=1e-5)
+
+
+def _x0(u, q):
+    su = np.sqrt(np.mean(u * u))
+    sq = np.sqrt(np.mean(q * q)) if q is not None else 1.0
+    qq = q / sq if q is not None else np.zeros_like(u)
+    return np.stack([to_bf16((u / su).astype(np.float32)), to_bf16(qq.astype(np.float32))]), su
+
+
+@pytest.mark.parametrize("circular", [False, True])
+def test_forward_end_to_end(circular):
+    grid, tau = (24, 20, 17), 1e-3
+    theta = cnn_init(11)
+    theta[-1] = 0.1
+    net = _net(grid, theta=theta)
+    net.set_hparams(out_scale=2.5)
+    u = normal_field(grid[::-1], 1)
+    q = normal_field(grid[::-1], 2) * 3
+    du = torch.empty(grid[::-1], dtype=torch.float32, device="cuda")
+    net.forward(dev(u), dev(q), du, circular, tau)
+    x0, su = _x0(u, q)
+    ref = cnn.forward(x0, theta, circular)[0] * tau * su * 2.5
+    got = host(du)
+    assert np.linalg.norm(got - ref) <= 5e-3 * np.linalg.norm(ref)
+    assert np.abs(got - ref).max() <= 3e-2 * np.abs(ref).max()
+
+
+def test_train_step_gradient_loss_and_adam():
+    grid, tau, batch = (16, 12, 10), 1e-3, 2
+    theta = cnn_init(12)
+    theta[-1] = 0.05
+    net = tbs.Net()
+    net.ensure_workspace(grid, batch, True)
+    net.set_weights(theta)
+    net.set_hparams(out_scale=1.5, lr=1e-3)
+    us = [normal_field(grid[::-1], 20 + b) for b in range(batch)]
+    qs = [normal_field(grid[::-1], 30 + b) for b in range(batch)]
+    ts = [normal_field(grid[::-1], 40 + b) * 1e-3 for b in range(batch)]
+    f32 = lambda a: np.stack(a).astype(np.float32).astype(np.float64)
+    U, Q, Tt = f32(us), f32(qs), f32(ts)
+    loss = net.train_step(dev(U, "f32"), dev(Q, "f32"), dev(Tt, "f32"), batch, False, tau)
+    grad = net.get_grad().astype(np.float64)
+    # oracle: mean over the batch of the per-sample losses / gradients (each sample normalised alone)
+    ref_loss, ref_grad = 0.0, np.zeros(cnn.N_PARAMS)
+    for b in range(batch):
+        x0, su = _x0(U[b], Q[b])
+        tgt = (Tt[b] / (tau * su * 1.5))[None]
+        l, gr = cnn.loss_and_grad(x0, theta, tgt, False)
+        ref_loss += l / batch
+        ref_grad += gr / batch
+    assert abs(loss - ref_loss) <= 1e-3 * ref_loss
+    assert np.linalg.norm(grad - ref_grad) <= 2e-2 * np.linalg.norm(ref_grad)
+    # first Adam step from zero moments: theta - lr g / (|g| + eps), on the device's own gradient
+    w1 = net.get_weights().astype(np.float64)
+    expect = theta.astype(np.float64) - 1e-3 * grad / (np.abs(grad) + 1e-8)
+    assert np.allclose(w1, expect, rtol=0, atol=2e-6)
+
+
+def test_training_reduces_loss_on_heat_pairs():
+    # learn u^{k+1} - u^k of the heat step on random smooth fields (24^3 Dirichlet cubic)
+    from workloads import gaussian_params, gaussian_sum
+    grid, n, tau = (24, 24, 24), 3, 2e-3
+    h = tuple(1.0 / (N + 1) for N in grid)
+    from oracle import exact
+    data = []
+    for s in range(6):
+        u = gaussian_sum(grid, "dirichlet", h, gaussian_params(100 + s, 8, 0.08, 0.2, 1.0, 0.2, 0.8))
+        q = gaussian_sum(grid, "dirichlet", h, gaussian_params(200 + s, 2, 0.08, 0.2, 10.0, 0.2, 0.8))
+        du = exact.step(u, q, n, h, tau, "dirichlet") - u
+        data.append((u, q, du))
+    net = tbs.Net()
+    net.ensure_workspace(grid, 2, True)
+    net.set_weights(cnn_init(5))
+    scale = np.sqrt(np.mean([np.mean((d / (tau * np.sqrt(np.mean(u * u)))) ** 2) for u, q, d in data]))
+    net.set_hparams(out_scale=scale, lr=2e-3)
+    losses = []
+    rng = np.random.default_rng(0)
+    for it in range(60):
+        idx = rng.choice(len(data), 2, replace=False)
+        U = dev(np.stack([data[i][0] for i in idx]), "f32")
+        Q = dev(np.stack([data[i][1] for i in idx]), "f32")
+        D = dev(np.stack([data[i][2] for i in idx]), "f32")
+        losses.append(net.train_step(U, Q, D, 2, False, tau))
+    assert np.mean(losses[-10:]) < 0.5 * np.mean(losses[:5]), losses
+
+
+def test_fallback_keeps_plain_path_with_useless_net():
+    grid, n, tau = (32, 24, 20), 3, 1e-3
+    h = tuple(1.0 / (N + 1) for N in grid)
+    u = normal_field(grid[::-1], 3)
+    theta = cnn_init(1)
+    theta[cnn.N_PARAMS - 1] = 100.0   # the guess adds a large constant: worse than u^k
+    net = tbs.Net()
+    net.ensure_workspace(grid, 1, False)
+    net.set_weights(theta)
+    ctx = tbs.Context(grid, n, h, tau, "dirichlet")
+    ctx.ensure_workspace(tbs.PREC_MIXED)
+    a, b = dev(np.zeros(grid[::-1])), dev(np.zeros(grid[::-1]))
+    s1 = ctx.timestep(dev(u), None, a, tbs.PREC_MIXED, 1e-8, 500, net)
+    s0 = ctx.timestep(dev(u), None, b, tbs.PREC_MIXED, 1e-8, 500, None)
+    assert s1["used_learned_guess"] == 0 and s1["rel_res_learned"] > s1["rel_res_plain"]
+    assert np.array_equal(host(a), host(b))
+    assert s1["iters"] == s0["iters"]

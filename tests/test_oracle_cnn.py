@@ -70,7 +70,7 @@ def test_rounded_forward_matches_torch_chain():
     # the rounded network equals torch conv3d + erf GELU applied on the same bf16 values
     x0 = normal_field((2, 5, 6, 4), 8)
     theta = cnn_init(9)
-    params = cnn.unpack(to_bf16(theta))
+    params = [(to_bf16(W), b) for W, b in cnn.unpack(theta)]
     a = to_bf16(x0)
     for li, (W, b) in enumerate(params):
         z = _torch_conv(a, W, b, False)
