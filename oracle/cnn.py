@@ -10,6 +10,10 @@ for periodic grids):
     y3 = GELU(W3 * y2 + b3)  16 -> 16
     o  =      W4 * y3 + b4   16 -> 1
 GELU is the exact erf form x/2 (1 + erf(x / sqrt 2)).  Parameter count 15,169.
+The network output is followed by a fixed low-pass filter B^2, B = Bx By Bz with the binomial
+taps [1/4, 1/2, 1/4] on each axis (zero padding / circular): a guess with grid-scale noise has
+error in the modes where A's eigenvalues are smallest, which CG converges on slowly.  B is
+symmetric, so the output gradient passes through the same filter.
 
 Rounding points (matching the device kernels, which multiply bf16 x bf16 and accumulate in
 fp32): every tensor that enters a product is rounded to bf16 first -- the inputs x0, the
@@ -25,6 +29,7 @@ from scipy.special import erf
 from .rounding import to_bf16
 
 LAYERS = ((2, 16), (16, 16), (16, 16), (16, 1))
+SMOOTH_PASSES = 2
 N_PARAMS = sum(ci * co * 27 + co for ci, co in LAYERS)
 
 
@@ -89,6 +94,20 @@ def conv3d_weight_grad(x, g, circular):
     return dW, g.sum(axis=(1, 2, 3))
 
 
+def smooth(o, circular, passes=SMOOTH_PASSES):
+    """B^passes o for o = [C, Z, Y, X]: binomial [1/4, 1/2, 1/4] along x, y and z."""
+    o = np.asarray(o, dtype=np.float64)
+    for _ in range(passes):
+        for ax in (3, 2, 1):
+            shape = [0, 0, 0]
+            d = [0, 0, 0]
+            d[ax - 1] = 1
+            lo = _shift(o, -d[0], -d[1], -d[2], circular)
+            hi = _shift(o, d[0], d[1], d[2], circular)
+            o = 0.25 * lo + 0.5 * o + 0.25 * hi
+    return o
+
+
 def unpack(theta):
     """Flat parameter vector -> [(W1, b1), ..., (W4, b4)] (order: W then b per layer)."""
     out, o = [], 0
@@ -123,7 +142,7 @@ def forward(x0, theta, circular, keep=False, rounding=True):
             a = rnd(gelu(z))
             acts.append(a)
         else:
-            o = z
+            o = smooth(z, circular)
     if keep:
         return o, acts, pre
     return o
@@ -141,7 +160,7 @@ def loss_and_grad(x0, theta, target, circular, rounding=True):
     o, acts, pre = forward(x0, theta, circular, keep=True, rounding=rounding)
     diff = o - target
     loss = float(np.mean(diff * diff))
-    g = rnd(2.0 * diff / diff.size)
+    g = rnd(smooth(2.0 * diff / diff.size, circular))
     grads = [None] * 4
     for li in range(3, -1, -1):
         W, _ = params[li]

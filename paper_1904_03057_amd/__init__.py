@@ -151,7 +151,7 @@ class Context:
         self._ws = None
 
     def __del__(self):
-        if getattr(self, "_h", None) is not None and self._h:
+        if _lib is not None and getattr(self, "_h", None) is not None and self._h:
             _lib.tbs_destroy(self._h)
             self._h = None
 
@@ -250,7 +250,7 @@ class Net:
         self._ws_key = None
 
     def __del__(self):
-        if getattr(self, "_h", None) is not None and self._h:
+        if _lib is not None and getattr(self, "_h", None) is not None and self._h:
             _lib.tbs_net_destroy(self._h)
             self._h = None
 

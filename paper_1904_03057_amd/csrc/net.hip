@@ -14,6 +14,7 @@
 // weights.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -32,6 +33,7 @@ constexpr int COUT[NL] = {16, 16, 16, 1};
 constexpr int NSTEP = 14;         // MFMA K-steps: 28 taps (27 + one zero) / 2
 constexpr int PACK = NSTEP * 64 * 8;  // bf16 per packed layer
 constexpr int WG_PARTS = 6928;    // max partial-gradient row: 16*16*27 weights + 16 biases
+constexpr int SMOOTH_PASSES = 2;  // passes of the separable binomial low-pass after the last layer
 
 __host__ __device__ constexpr int woff(int l) {  // offset of W_l in the flat parameter vector
   return l == 0 ? 0 : woff(l - 1) + CIN[l - 1] * COUT[l - 1] * 27 + COUT[l - 1];
@@ -339,22 +341,47 @@ __global__ __launch_bounds__(256) void prep_input(const T* __restrict__ u, const
   }
 }
 
-// loss partials and output gradient: t = du / sc2, diff = o - t, g = bf16(2 diff / total)
+// loss partials and output gradient: t = du / sc2, diff = o - t, g = 2 diff / total (fp32; it is
+// smoothed by the adjoint of the output filter and rounded to bf16 afterwards)
 __global__ __launch_bounds__(256) void mse_grad(const float* __restrict__ o, const float* __restrict__ du, int64_t n,
                                                 const double* __restrict__ sc, double inv_total,
-                                                uint16_t* __restrict__ gout, double* part) {
+                                                float* __restrict__ gout, double* part) {
   __shared__ double red[4];
   const double s = sc[2];
   double acc = 0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
     const double d = (double)o[i] - (double)du[i] / s;
     acc = fma(d, d, acc);
-    gout[i] = f32_to_bf16((float)(2.0 * d * inv_total));
+    gout[i] = (float)(2.0 * d * inv_total);
   }
   acc = wave_sum(acc);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;
   __syncthreads();
   if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// One axis of the output low-pass filter: dst = [1/4, 1/2, 1/4] * src along `axis` (0 x, 1 y, 2 z),
+// zero outside a Dirichlet grid, wrapped on a periodic one.  Symmetric, so it is its own adjoint.
+__global__ __launch_bounds__(256) void smooth_axis(const float* __restrict__ src, float* __restrict__ dst, Grid3 g,
+                                                   int axis) {
+  const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+  const int64_t stride = axis == 0 ? 1 : (axis == 1 ? (int64_t)g.nx : (int64_t)g.nx * g.ny);
+  const int n = axis == 0 ? g.nx : (axis == 1 ? g.ny : g.nz);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
+    const int c = (int)((i / stride) % n);
+    float l = 0.f, r = 0.f;
+    if (c > 0) l = src[i - stride];
+    else if (g.periodic) l = src[i + (int64_t)(n - 1) * stride];
+    if (c < n - 1) r = src[i + stride];
+    else if (g.periodic) r = src[i - (int64_t)(n - 1) * stride];
+    dst[i] = 0.25f * l + 0.5f * src[i] + 0.25f * r;
+  }
+}
+
+__global__ __launch_bounds__(256) void f32_to_bf16_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst,
+                                                          int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    dst[i] = f32_to_bf16(src[i]);
 }
 
 __global__ void loss_final(const double* __restrict__ part, int blocks, double inv_total, double* loss_acc,
@@ -600,6 +627,8 @@ static int conv_blocks(const int64_t grid[3]) {
   return (int)(((grid[0] + CTX - 1) / CTX) * ((grid[1] + CTY - 1) / CTY) * ((grid[2] + CTZ - 1) / CTZ));
 }
 
+static int smooth(tbs_net* n, float* buf, float* tmp, Grid3 g);
+
 // forward of one sample; x0 already prepared.  keep = training (store z and all y, and leave the
 // network output unscaled for the loss); otherwise the output is the guess du = o * sc[2].
 static int forward_layers(tbs_net* n, Grid3 g, int keep) {
@@ -618,6 +647,23 @@ static int forward_layers(tbs_net* n, Grid3 g, int keep) {
   hipLaunchKernelGGL((conv_mfma<16, 1, EPI_LINEAR>), dim3(nb), dim3(256), 0, n->st, (const uint16_t*)y2,
                      w.wf + 3 * PACK, w.bias + 48, g, nullptr, nullptr, w.o, nullptr,
                      (const double*)(w.sc + (keep ? 3 : 2)));
+  NCHK(hipGetLastError());
+  // output low-pass (linear, so it commutes with the output scale); scratch: a free activation buffer
+  return smooth(n, w.o, keep ? (float*)w.gz[0] : (float*)w.y[1], g);
+}
+
+// buf <- B^SMOOTH_PASSES buf with B = Bx By Bz the binomial low-pass; tmp is scratch of N floats
+static int smooth(tbs_net* n, float* buf, float* tmp, Grid3 g) {
+  const int64_t N = (int64_t)g.nx * g.ny * g.nz;
+  int blocks = (int)std::min<int64_t>((N + 255) / 256, 8192);
+  float* a = buf;
+  float* b = tmp;
+  for (int p = 0; p < SMOOTH_PASSES; ++p)
+    for (int ax = 0; ax < 3; ++ax) {
+      hipLaunchKernelGGL(smooth_axis, dim3(blocks), dim3(256), 0, n->st, (const float*)a, b, g, ax);
+      float* t = a; a = b; b = t;
+    }
+  if (a != buf) NCHK(hipMemcpyAsync(buf, a, (size_t)N * 4, hipMemcpyDeviceToDevice, n->st));
   NCHK(hipGetLastError());
   return TBS_OK;
 }
@@ -688,8 +734,12 @@ extern "C" int tbs_net_train_step(tbs_net* n, const float* u, const float* q, co
     if (rc) return rc;
     rc = forward_layers(n, g, 1);
     if (rc) return rc;
+    float* gtmp = (float*)w.gz[0];
     hipLaunchKernelGGL(mse_grad, dim3(kRedBlocks), dim3(256), 0, n->st, (const float*)w.o, tb, N,
-                       (const double*)w.sc, inv_total, w.gout, w.red);
+                       (const double*)w.sc, inv_total, gtmp, w.red);
+    rc = smooth(n, gtmp, (float*)w.gz[1], g);  // adjoint of the output filter (it is symmetric)
+    if (rc) return rc;
+    hipLaunchKernelGGL(f32_to_bf16_kernel, dim3(2048), dim3(256), 0, n->st, (const float*)gtmp, w.gout, N);
     hipLaunchKernelGGL(loss_final, dim3(1), dim3(64), 0, n->st, (const double*)w.red, kRedBlocks, inv_total,
                        w.sc + 4, b > 0);
     const int acc = b > 0;

@@ -1,0 +1,210 @@
+"""Train and evaluate the learned CG initial guess with the library's own GPU kernels.
+
+Train (dataset from the library's FP64 implicit steps, 2000 Adam steps, batch 4):
+    python paper_1904_03057_amd/train_guess.py train --out paper_1904_03057_amd/weights/guess_net_128
+        [--grid 128] [--h 1/129] [--tau 1e-4] [--traj 40] [--len 10] [--steps 2000] [--batch 4]
+Evaluate learned vs plain guess over implicit steps (refined FP32 CG to 1e-8):
+    python paper_1904_03057_amd/train_guess.py eval --weights paper_1904_03057_amd/weights/guess_net_128
+        [--grid 512] [--h 1/513] [--tau 1e-4] [--steps 50]
+
+Inputs are seeded Gaussian sums (initial fields: 16 terms, sigma in [0.02, 0.1], amplitudes
+N(0,1); sources: 1-4 terms, sigma in [0.05, 0.15], amplitudes 10 N(0,1)), centres uniform in
+the middle 80% of the box.  Weights are written as raw little-endian fp32 (<out>.f32) with a
+JSON description (<out>.json: output scale, grid, spacing, time step, loss curve, held-out gain).
+Prints one JSON line per command.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def _frac(s):
+    if "/" in s:
+        a, b = s.split("/")
+        return float(a) / float(b)
+    return float(s)
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def fields(grid, h, seed, torch):
+    import numpy as np
+
+    import workloads
+    L = (grid[0] + 1) * h[0]
+    pu = workloads.gaussian_params(seed, 16, 0.02, 0.1, 1.0, 0.1 * L, 0.9 * L)
+    rng = np.random.default_rng(seed + 17)
+    pq = workloads.gaussian_params(seed + 31, int(rng.integers(1, 5)), 0.05, 0.15, 10.0, 0.1 * L, 0.9 * L)
+    u = workloads.gaussian_sum(grid, "dirichlet", h, pu, xp=torch, device="cuda", dtype=torch.float64)
+    q = workloads.gaussian_sum(grid, "dirichlet", h, pq, xp=torch, device="cuda", dtype=torch.float64)
+    return u, q
+
+
+def cmd_train(a):
+    import numpy as np
+    import torch
+
+    import paper_1904_03057_amd as tbs
+    import workloads
+
+    grid = (a.grid,) * 3
+    h = (_frac(a.h),) * 3
+    tau = a.tau
+    ctx = tbs.Context(grid, 3, h, tau, "dirichlet")
+    ctx.ensure_workspace(tbs.PREC_FP64)
+    t0 = time.perf_counter()
+    U, Q, D = [], [], []
+    iters = []
+    for t in range(a.traj):
+        u, q = fields(grid, h, 1000 + t, torch)
+        for k in range(a.len):
+            un = torch.empty_like(u)
+            st = ctx.timestep(u, q, un, tbs.PREC_FP64, 1e-10, 2000)
+            iters.append(st["iters"])
+            U.append(u.float())
+            Q.append(q.float())
+            D.append((un - u).float())
+            u = un
+        log("trajectory %d done (%d pairs)" % (t, len(U)))
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    n_pairs = len(U)
+    n_val = max(1, n_pairs // 10)
+    train_idx = np.arange(n_pairs - n_val)
+    val_idx = np.arange(n_pairs - n_val, n_pairs)
+    # output scale: RMS of du / (tau * rms(u)) over the training pairs (a fixed data statistic)
+    ratios = [float(torch.sqrt(torch.mean((D[i].double() / (tau * torch.sqrt(torch.mean(U[i].double() ** 2)))) ** 2)))
+              for i in train_idx]
+    out_scale = float(np.sqrt(np.mean(np.square(ratios))))
+    net = tbs.Net()
+    net.ensure_workspace(grid, a.batch, True)
+    net.set_weights(workloads.cnn_init(a.seed))
+    net.set_hparams(out_scale=out_scale, lr=a.lr)
+    rng = np.random.default_rng(a.seed)
+    losses = []
+    t1 = time.perf_counter()
+    for s in range(a.steps):
+        idx = rng.choice(train_idx, a.batch, replace=False)
+        ub = torch.stack([U[i] for i in idx]).contiguous()
+        qb = torch.stack([Q[i] for i in idx]).contiguous()
+        db = torch.stack([D[i] for i in idx]).contiguous()
+        losses.append(net.train_step(ub, qb, db, a.batch, False, tau, want_loss=(s % 10 == 0 or s == a.steps - 1)))
+        if s % 100 == 0 or s == a.steps - 1:
+            log("step %d loss %.5f" % (s, losses[-1]))
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    # held-out gain: FP64 residual of u + du relative to that of the plain guess u
+    net.ensure_workspace(grid, 1, False)
+    gains = []
+    for i in val_idx:
+        u, q = U[i].double(), Q[i].double()
+        b = torch.empty_like(u)
+        ctx.rhs(u, q, b)
+        du = torch.empty(u.shape, dtype=torch.float32, device="cuda")
+        net.forward(u, q, du, False, tau)
+        rp, bn = ctx.residual(u, b)
+        rl, _ = ctx.residual(u + du.double(), b)
+        gains.append(rl / rp)
+    w = net.get_weights()
+    os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+    w.astype("<f4").tofile(a.out + ".f32")
+    meta = {"grid": list(grid), "h": h[0], "tau": tau, "degree": 3, "bc": "dirichlet", "out_scale": out_scale,
+            "lr": a.lr, "steps": a.steps, "batch": a.batch, "pairs": n_pairs, "train_pairs": int(len(train_idx)),
+            "loss_first": [l for l in losses[:50] if l is not None][:5],
+            "loss_last": [l for l in losses[-50:] if l is not None][-5:],
+            "loss_curve": [(i, l) for i, l in enumerate(losses) if l is not None and i % 50 == 0],
+            "heldout_res_ratio_mean": float(np.mean(gains)), "heldout_res_ratio_max": float(np.max(gains)),
+            "dataset_solver_iters_mean": float(np.mean(iters)), "seconds_dataset": t_data,
+            "seconds_train": t_train}
+    with open(a.out + ".json", "w") as f:
+        json.dump(meta, f, indent=1)
+    print(json.dumps({k: meta[k] for k in ("out_scale", "loss_first", "loss_last", "heldout_res_ratio_mean",
+                                            "heldout_res_ratio_max", "seconds_dataset", "seconds_train")}),
+          flush=True)
+
+
+def cmd_eval(a):
+    import numpy as np
+    import torch
+
+    import paper_1904_03057_amd as tbs
+
+    grid = (a.grid,) * 3
+    h = (_frac(a.h),) * 3
+    tau = a.tau
+    meta = json.load(open(a.weights + ".json"))
+    w = np.fromfile(a.weights + ".f32", dtype="<f4")
+    stream = torch.cuda.current_stream()
+    ctx = tbs.Context(grid, 3, h, tau, "dirichlet", stream=stream)
+    ctx.set_opts(poll_every=2)
+    ctx.ensure_workspace(tbs.PREC_MIXED)
+    net = tbs.Net(stream=stream)
+    net.ensure_workspace(grid, 1, False)
+    net.set_weights(w)
+    net.set_hparams(out_scale=meta["out_scale"])
+    res = {}
+    for name, use in (("plain", False), ("learned", True)):
+        u, q = fields(grid, h, a.seed, torch)
+        un = torch.empty_like(u)
+        ctx.timestep(u, q, un, tbs.PREC_MIXED, a.rtol, 5000, net if use else None)  # warm-up
+        torch.cuda.synchronize()
+        its, used, ratios, times = [], [], [], []
+        for s in range(a.steps):
+            t0 = time.perf_counter()
+            st = ctx.timestep(u, q, un, tbs.PREC_MIXED, a.rtol, 5000, net if use else None)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            its.append(st["iters"])
+            used.append(st["used_learned_guess"])
+            if use:
+                ratios.append(st["rel_res_learned"] / st["rel_res_plain"])
+            u, un = un, u
+        res[name] = {"iters_mean": float(np.mean(its)), "iters": its, "s_per_step_mean": float(np.mean(times)),
+                     "s_total": float(np.sum(times)), "learned_used": int(np.sum(used)),
+                     "res_ratio_mean": float(np.mean(ratios)) if ratios else None}
+        log("%s: iters %.2f  s/step %.4f  used %d" % (name, res[name]["iters_mean"], res[name]["s_per_step_mean"],
+                                                     res[name]["learned_used"]))
+    out = {"grid": list(grid), "h": h[0], "tau": tau, "steps": a.steps, "rtol": a.rtol,
+           "weights": os.path.basename(a.weights), "trained_on": {k: meta[k] for k in ("grid", "h", "tau")},
+           "plain": res["plain"], "learned": res["learned"],
+           "iters_saved_per_step": res["plain"]["iters_mean"] - res["learned"]["iters_mean"],
+           "speedup": res["plain"]["s_per_step_mean"] / res["learned"]["s_per_step_mean"]}
+    print(json.dumps(out), flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    t = sub.add_parser("train")
+    t.add_argument("--out", required=True)
+    t.add_argument("--grid", type=int, default=128)
+    t.add_argument("--h", default="1/129")
+    t.add_argument("--tau", type=float, default=1e-4)
+    t.add_argument("--traj", type=int, default=40)
+    t.add_argument("--len", type=int, default=10)
+    t.add_argument("--steps", type=int, default=2000)
+    t.add_argument("--batch", type=int, default=4)
+    t.add_argument("--lr", type=float, default=1e-3)
+    t.add_argument("--seed", type=int, default=5)
+    e = sub.add_parser("eval")
+    e.add_argument("--weights", required=True)
+    e.add_argument("--grid", type=int, default=512)
+    e.add_argument("--h", default="1/513")
+    e.add_argument("--tau", type=float, default=1e-4)
+    e.add_argument("--steps", type=int, default=50)
+    e.add_argument("--rtol", type=float, default=1e-8)
+    e.add_argument("--seed", type=int, default=55)
+    a = ap.parse_args()
+    (cmd_train if a.cmd == "train" else cmd_eval)(a)
+
+
+if __name__ == "__main__":
+    main()

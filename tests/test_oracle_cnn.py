@@ -75,7 +75,25 @@ def test_rounded_forward_matches_torch_chain():
     for li, (W, b) in enumerate(params):
         z = _torch_conv(a, W, b, False)
         a = to_bf16(0.5 * z * (1 + torch.erf(torch.from_numpy(z) / np.sqrt(2)).numpy())) if li < 3 else z
+    k1 = np.array([0.25, 0.5, 0.25])
+    K = np.einsum("i,j,k->ijk", k1, k1, k1)[None, None]
+    for _ in range(cnn.SMOOTH_PASSES):
+        a = _torch_conv(a, K, None, False)
     assert np.allclose(cnn.forward(x0, theta, False), a, atol=1e-10)
+
+
+@pytest.mark.parametrize("circular", [False, True])
+def test_output_filter_symbol_and_adjoint(circular):
+    # a Fourier mode on a periodic grid is scaled by prod_d cos^4(w_d / 2); the filter is symmetric
+    N = 16
+    x = np.arange(N)
+    w = [2 * np.pi * k / N for k in (1, 3, 5)]
+    mode = np.cos(w[2] * x[:, None, None] + w[1] * x[None, :, None] + w[0] * x[None, None, :])[None]
+    if circular:
+        expect = np.prod([np.cos(wi / 2) ** (2 * cnn.SMOOTH_PASSES) for wi in w])
+        assert np.allclose(cnn.smooth(mode, True), expect * mode, atol=1e-13)
+    a, b = normal_field((1, 7, 6, 5), 1), normal_field((1, 7, 6, 5), 2)
+    assert abs(np.sum(cnn.smooth(a, circular) * b) - np.sum(a * cnn.smooth(b, circular))) < 1e-12
 
 
 def test_adam_first_step_closed_form():
