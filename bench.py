@@ -22,7 +22,9 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GDoF/s of (M+τΣK)u apply; s per implicit step at 0.8B DoF, learned vs plain CG"
 HBM_PEAK_GBS = 8000.0
-WEIGHTS = os.path.join(ROOT, "paper_1904_03057_amd", "weights", "guess_net_128.f32")
+# network trained by paper_1904_03057_amd/train_guess.py on 128^3 windows at this workload's grid
+# spacing and time step (h = 1/929, tau = 1e-5)
+WEIGHTS = os.path.join(ROOT, "paper_1904_03057_amd", "weights", "guess_net_928w")
 
 
 def log(*a):
@@ -39,7 +41,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="only the timed steps (for profiling runs)")
     ap.add_argument("--probe", default=None,
                     help="run one kernel kind --steps times for counter collection instead of the benchmark: "
-                         "apply_f64 | apply_f32 | apply_bf16 | copy (f64->f32 conversion, the traffic calibration)")
+                         "apply_f64 | apply_f32 | apply_bf16 | net (network guess) | "
+                         "copy (f64->f32 conversion, the traffic calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path (the design notes "
@@ -73,10 +76,11 @@ def main():
         ctx.set_opts(poll_every=1)
         ctx.ensure_workspace(tbs.PREC_MIXED)
     net = None
-    if os.path.exists(WEIGHTS):
+    if os.path.exists(WEIGHTS + ".f32") and args.workload == "heat928":
         net = tbs.Net(stream=stream)
-        net.set_weights(np.fromfile(WEIGHTS, dtype=np.float32))
         net.ensure_workspace(w.grid, 1, False)
+        net.set_weights(np.fromfile(WEIGHTS + ".f32", dtype="<f4"))
+        net.set_hparams(out_scale=json.load(open(WEIGHTS + ".json"))["out_scale"])
     torch.cuda.synchronize()
 
     def step(prec, use_net):
@@ -144,6 +148,7 @@ def main():
 
 def probe(args):
     """One kernel kind, --steps launches on the 928^3 field (for rocprofv3 counter passes)."""
+    import numpy as np
     import torch
 
     import paper_1904_03057_amd as tbs
@@ -171,12 +176,22 @@ def probe(args):
         dst = torch.empty(u.shape, dtype=torch.float32, device="cuda")
         run = lambda: ctx.apply(src, dst)
         nbytes = 6 * N
+    elif kind == "net":
+        net = tbs.Net()
+        net.ensure_workspace(w.grid, 1, False)
+        net.set_weights(np.fromfile(WEIGHTS + ".f32", dtype="<f4"))
+        net.set_hparams(out_scale=json.load(open(WEIGHTS + ".json"))["out_scale"])
+        du = torch.empty(u.shape, dtype=torch.float32, device="cuda")
+        run = lambda: net.forward(u, None, du, False, w.tau)
+        nbytes = 0
     elif kind == "copy":
         dst = torch.empty(u.shape, dtype=torch.float32, device="cuda")
         run = lambda: ctx.convert(u, dst)
         nbytes = 12 * N
     else:
         raise SystemExit("unknown probe " + kind)
+    for _ in range(2):  # warm-up (code-object load, caches)
+        run()
     torch.cuda.synchronize()
     ctx.prof_enable(True)
     for i in range(args.steps):
@@ -240,6 +255,18 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N):
                     "learned_used": [s["used_learned_guess"] for s in sts]}
         log("%s: %s" % (name, sp[name]))
     res["s_per_step"] = sp
+    if net is not None:
+        du = torch.empty(u0.shape, dtype=torch.float32, device="cuda")
+        for _ in range(2):
+            net.forward(u0, None, du, False, w.tau)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(3):
+            net.forward(u0, None, du, False, w.tau)
+        torch.cuda.synchronize()
+        res["net_forward_s"] = round((time.perf_counter() - t0) / 3, 4)
+        log("net forward: %.4f s" % res["net_forward_s"])
+        del du
     return res
 
 

@@ -400,7 +400,7 @@ static int resid_async(tbs_ctx* c, const double* x, const double* b, void* r, in
   const int ps = prof_begin(c, 8, -1, (double)c->N * (16 + (r ? (r_dt == TBS_F32 ? 4 : 8) : 0)));
   HIPCHK(launch_resid(a, c->n, c->bc, r_dt == TBS_F32 ? 1 : 0, c->st));
   prof_end(c, ps);
-  HIPCHK(launch_finalize(fin_op, part0(c), part1(c), c->nblocks, scal(c, slot), rtol, c->st));
+  HIPCHK(launch_finalize(fin_op, part0(c), part1(c), stencil_blocks(a, M_RESID, 8), scal(c, slot), rtol, c->st));
   return TBS_OK;
 }
 
@@ -471,7 +471,8 @@ static int cg1_async(tbs_ctx* c, const CgArrays& A, int dt, int k) {
   int ps = prof_begin(c, 5 + dt, k, b1);
   HIPCHK(launch_cg1(a, c->n, c->bc, dt, c->st));
   prof_end(c, ps);
-  HIPCHK(launch_finalize(FIN_ALPHA, part0(c), nullptr, c->nblocks, scal(c, SC_CG), 0.0, c->st));
+  HIPCHK(launch_finalize(FIN_ALPHA, part0(c), nullptr, stencil_blocks(a, M_CG1, dt == 0 ? 8 : 4), scal(c, SC_CG),
+                         0.0, c->st));
   ps = prof_begin(c, dt == 0 ? 9 : 10, k, (double)c->N * 3 * tc);
   HIPCHK(launch_cg2(A.r, A.q, c->N, dt == 0 ? 0 : 1, part0(c), scal(c, SC_CG), c->st));
   prof_end(c, ps);
@@ -613,9 +614,11 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
   // initial guess: plain u^k, or the network guess if its FP64 residual is smaller
   rc = copy_async(c, u_next, u_prev, N * 8);
   if (rc) return rc;
+  // refined path: the plain guess's residual (FP32 copy, norms and partial sums) is the first
+  // refinement sweep's residual whenever the plain guess is kept, so it is computed last and reused
+  bool have_res0 = false;
+  Scalars res0{};
   if (net && prec != TBS_PREC_FP32) {
-    rc = fp64_relres(c, u_prev, b64, &st.rel_res_plain);
-    if (rc) return rc;
     const float* du = nullptr;
     const int64_t grid[3] = {c->nx, c->ny, c->nz};
     rc = tbs_net_guess_internal(net, grid, c->bc == TBS_BC_PERIODIC, c->tau, c->st, u_prev, q, &du);
@@ -623,11 +626,22 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     HIPCHK(launch_guess_combine(u_next, u_prev, du, c->N, c->st));
     rc = fp64_relres(c, u_next, b64, &st.rel_res_learned);
     if (rc) return rc;
+    if (prec == TBS_PREC_MIXED || prec == TBS_PREC_MIXED_BF16) {
+      rc = resid_async(c, u_prev, b64, c->ws + L.off[1], TBS_F32, SC_AUX, FIN_NORMS, 0.0);
+      if (rc) return rc;
+      rc = read_scal(c, SC_AUX, &res0);
+      if (rc) return rc;
+      st.rel_res_plain = res0.out2 > 0 ? std::sqrt(res0.out / res0.out2) : std::sqrt(res0.out);
+    } else {
+      rc = fp64_relres(c, u_prev, b64, &st.rel_res_plain);
+      if (rc) return rc;
+    }
     if (st.rel_res_learned < st.rel_res_plain) {
       st.used_learned_guess = 1;
     } else {
       rc = copy_async(c, u_next, u_prev, N * 8);
       if (rc) return rc;
+      have_res0 = (prec == TBS_PREC_MIXED || prec == TBS_PREC_MIXED_BF16);
     }
   }
 
@@ -684,11 +698,15 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     CgArrays A{d32, r32, {c->ws + L.off[3], c->ws + L.off[4]}, c->ws + L.off[5]};
     int total = 0, sweeps = 0;
     for (;;) {
-      rc = resid_async(c, u_next, b64, r32, TBS_F32, SC_AUX, FIN_NORMS, 0.0);
-      if (rc) return rc;
       Scalars s;
-      rc = read_scal(c, SC_AUX, &s);
-      if (rc) return rc;
+      if (sweeps == 0 && have_res0) {
+        s = res0;  // r32 and the residual partial sums of u_next = u_prev are already in place
+      } else {
+        rc = resid_async(c, u_next, b64, r32, TBS_F32, SC_AUX, FIN_NORMS, 0.0);
+        if (rc) return rc;
+        rc = read_scal(c, SC_AUX, &s);
+        if (rc) return rc;
+      }
       const double rel = s.out2 > 0 ? std::sqrt(s.out / s.out2) : std::sqrt(s.out);
       if (sweeps == 0) {
         st.rel_res0 = rel;
@@ -701,7 +719,8 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
       // inner solve A d = r32 from d = 0 to relative tolerance eta (no tighter than needed)
       const double eta = std::max(c->opts.inner_rtol, 0.5 * rtol / rel);
       HIPCHK(launch_fill(d32, 1, c->N, c->st));
-      HIPCHK(launch_finalize(FIN_INIT, part0(c), part0(c), c->nblocks, scal(c, SC_CG), eta, c->st));
+      HIPCHK(launch_finalize(FIN_INIT, part0(c), part0(c), stencil_blocks(base_args(c), M_RESID, 8), scal(c, SC_CG),
+                             eta, c->st));
       int nit = 0;
       const int cap = std::min(c->opts.inner_max_iter, std::max(1, max_iter - total));
       int irc = cg_loop(c, A, dt, 0, cap, &nit);

@@ -63,106 +63,139 @@ constexpr int CTX = 16, CTY = 8, CTZ = 4;             // output tile (x, y, z)
 constexpr int SX = CTX + 2, SY = CTY + 2, SZ = CTZ + 2;  // staged tile
 constexpr int SVOX = SX * SY * SZ;
 
-// in: [voxel][CIS] bf16; wpk: packed A operands [NSTEP][64 lanes][8]; out per epilogue:
+// in: [voxel][CIS] bf16; wpk: packed A operands [steps][64 lanes][8]; out per epilogue:
 //   EPI_GELU:   zout (f32 [voxel][16], nullable) = acc + bias; yout (bf16 [voxel][16]) = GELU(z)
 //   EPI_LINEAR: fout (f32 [voxel]) = (acc[0] + bias[0]) * (*scale)          (last layer, 1 channel)
 //   EPI_BWD:    yout (bf16 [voxel][16]) = acc * GELU'(zprev[voxel][c])       (backward data)
 //   EPI_RAW:    fout (f32 [voxel][COS]) = acc (+ bias if bias != NULL)       (parity probes)
+// Two K layouts: with 16 (or zero-padded 1) input channels each K-step holds 2 taps x 16
+// channels (14 steps); with 2 input channels it holds 16 taps x 2 channels (2 steps, 27 taps
+// padded to 32), and the tile keeps only the 2 channels in LDS.  Workgroups are persistent:
+// they load the weights once and loop over tiles.
 template <int CIS, int COS, int EPI>
 __global__ __launch_bounds__(256) void conv_mfma(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
                                                  const float* __restrict__ bias, Grid3 g,
                                                  float* __restrict__ zout, uint16_t* __restrict__ yout,
                                                  float* __restrict__ fout, const float* __restrict__ zprev,
                                                  const double* __restrict__ scale) {
-  __shared__ __attribute__((aligned(16))) uint16_t st[SVOX * 16];
+  constexpr bool TWO = (CIS == 2);
+  constexpr int STEPS = TWO ? 2 : NSTEP;
+  constexpr int VW = TWO ? 2 : 16;     // bf16 per staged voxel
+  __shared__ __attribute__((aligned(16))) uint16_t st[SVOX * VW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tx = (g.nx + CTX - 1) / CTX, ty = (g.ny + CTY - 1) / CTY;
-  int b = blockIdx.x;
-  const int bx = b % tx; b /= tx;
-  const int by = b % ty;
-  const int bz = b / ty;
-  const int x0 = bx * CTX, y0 = by * CTY, z0 = bz * CTZ;
+  const int tx = (g.nx + CTX - 1) / CTX, ty = (g.ny + CTY - 1) / CTY, tz = (g.nz + CTZ - 1) / CTZ;
+  const int ntiles = tx * ty * tz;
   const int64_t plane = (int64_t)g.nx * g.ny;
 
-  // stage the input tile: 16 channels per voxel (channels >= CIS are zero)
-  for (int v = tid; v < SVOX; v += 256) {
-    const int sx = v % SX, sy = (v / SX) % SY, sz = v / (SX * SY);
-    int gx = x0 + sx - 1, gy = y0 + sy - 1, gz = z0 + sz - 1;
-    bool ok = true;
-    if (g.periodic) {
-      gx = (gx + g.nx) % g.nx; gy = (gy + g.ny) % g.ny; gz = (gz + g.nz) % g.nz;
-    } else {
-      ok = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
-    }
-    uint4 lo = make_uint4(0, 0, 0, 0), hi = make_uint4(0, 0, 0, 0);
-    if (ok) {
-      const int64_t vi = (int64_t)gz * plane + (int64_t)gy * g.nx + gx;
-      if (CIS == 16) {
-        const uint4* p = (const uint4*)(in + vi * 16);
-        lo = p[0];
-        hi = p[1];
-      } else if (CIS == 2) {
-        lo.x = *(const uint32_t*)(in + vi * 2);
-      } else {
-        lo.x = in[vi];
-      }
-    }
-    uint4* d = (uint4*)(st + v * 16);
-    d[0] = lo;
-    d[1] = hi;
-  }
-
-  // A operands (weights) for all 14 K-steps, kept in registers
-  bf16x8 wa[NSTEP];
+  // A operands (weights) for all K-steps, loaded once and kept in registers
+  bf16x8 wa[STEPS];
 #pragma unroll
-  for (int s = 0; s < NSTEP; ++s) wa[s] = *(const bf16x8*)(wpk + (s * 64 + lane) * 8);
-  __syncthreads();
-
-  const int grp = lane >> 4;          // K-group of this lane: tap 2s + grp/2, channels 8(grp&1)..+7
+  for (int s = 0; s < STEPS; ++s) wa[s] = *(const bf16x8*)(wpk + (s * 64 + lane) * 8);
+  float bz[4] = {0.f, 0.f, 0.f, 0.f};
+  const int grp = lane >> 4;          // K-group of this lane
   const int vx = lane & 15;           // voxel (x) of this lane's B column / D column
-  const int chalf = (grp & 1) * 8;
-  // each wave: rows (y, z) of the tile, 16 voxels along x per row
-  for (int row = wave; row < CTY * CTZ; row += 4) {
-    const int ry = row % CTY, rz = row / CTY;
-    f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  const int c0 = 4 * grp;             // D rows (output channels) held by this lane
+  if (bias)
 #pragma unroll
-    for (int s = 0; s < NSTEP; ++s) {
-      int tap = 2 * s + (grp >> 1);
-      if (tap > 26) tap = 13;  // padding tap: zero weights, any finite data (the centre)
-      const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
-      const int sv = ((rz + dz) * SY + (ry + dy)) * SX + (vx + dx);
-      const bf16x8 bv = *(const bf16x8*)(st + sv * 16 + chalf);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s], bv, acc, 0, 0, 0);
-    }
-    // D layout: acc[r] = Out[channel 4*grp + r][voxel vx]
-    const int gx = x0 + vx, gy = y0 + ry, gz = z0 + rz;
-    if (gx < g.nx && gy < g.ny && gz < g.nz) {
-      const int64_t vi = (int64_t)gz * plane + (int64_t)gy * g.nx + gx;
-      const int c0 = 4 * grp;
-      if (EPI == EPI_GELU) {
-        float z[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) z[r] = acc[r] + bias[c0 + r];
-        if (zout) *(float4*)(zout + vi * 16 + c0) = make_float4(z[0], z[1], z[2], z[3]);
-        uint2 packed;
-        packed.x = (uint32_t)f32_to_bf16(gelu_f(z[0])) | ((uint32_t)f32_to_bf16(gelu_f(z[1])) << 16);
-        packed.y = (uint32_t)f32_to_bf16(gelu_f(z[2])) | ((uint32_t)f32_to_bf16(gelu_f(z[3])) << 16);
-        *(uint2*)(yout + vi * 16 + c0) = packed;
-      } else if (EPI == EPI_LINEAR) {
-        if (grp == 0) fout[vi] = (float)(((double)acc[0] + (double)bias[0]) * scale[0]);
-      } else if (EPI == EPI_BWD) {
-        const float4 zp = *(const float4*)(zprev + vi * 16 + c0);
-        uint2 packed;
-        packed.x = (uint32_t)f32_to_bf16(acc[0] * gelu_grad_f(zp.x)) |
-                   ((uint32_t)f32_to_bf16(acc[1] * gelu_grad_f(zp.y)) << 16);
-        packed.y = (uint32_t)f32_to_bf16(acc[2] * gelu_grad_f(zp.z)) |
-                   ((uint32_t)f32_to_bf16(acc[3] * gelu_grad_f(zp.w)) << 16);
-        *(uint2*)(yout + vi * 16 + c0) = packed;
+    for (int r = 0; r < 4; ++r) bz[r] = (c0 + r < COS) ? bias[c0 + r] : 0.f;
+
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int bx = tile % tx, by = (tile / tx) % ty, bzt = tile / (tx * ty);
+    const int x0 = bx * CTX, y0 = by * CTY, z0 = bzt * CTZ;
+    __syncthreads();  // previous tile's reads of st are done
+    for (int v = tid; v < SVOX; v += 256) {
+      const int sx = v % SX, sy = (v / SX) % SY, sz = v / (SX * SY);
+      int gx = x0 + sx - 1, gy = y0 + sy - 1, gz = z0 + sz - 1;
+      bool ok = true;
+      if (g.periodic) {
+        gx = (gx + g.nx) % g.nx; gy = (gy + g.ny) % g.ny; gz = (gz + g.nz) % g.nz;
       } else {
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (c0 + r < COS) fout[vi * COS + c0 + r] = acc[r] + (bias ? bias[c0 + r] : 0.f);
+        ok = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
       }
+      const int64_t vi = (int64_t)gz * plane + (int64_t)gy * g.nx + gx;
+      if (TWO) {
+        *(uint32_t*)(st + v * 2) = ok ? *(const uint32_t*)(in + vi * 2) : 0u;
+      } else {
+        uint4 lo = make_uint4(0, 0, 0, 0), hi = make_uint4(0, 0, 0, 0);
+        if (ok) {
+          if (CIS == 16) {
+            const uint4* p = (const uint4*)(in + vi * 16);
+            lo = p[0];
+            hi = p[1];
+          } else {
+            lo.x = in[vi];
+          }
+        }
+        uint4* d = (uint4*)(st + v * 16);
+        d[0] = lo;
+        d[1] = hi;
+      }
+    }
+    __syncthreads();
+
+    // B operand of K-step s for tile row `row` (16 voxels along x)
+    auto bop = [&](int row, int s) -> bf16x8 {
+      const int ry = row % CTY, rz = row / CTY;
+      bf16x8 bv;
+      if (TWO) {
+        // k = 8 grp + j: tap 16 s + 4 grp + j/2, channel j % 2
+        uint32_t w4[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          int tap = 16 * s + 4 * grp + t;
+          if (tap > 26) tap = 13;  // padding taps: zero weights, finite data
+          const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
+          w4[t] = *(const uint32_t*)(st + (((rz + dz) * SY + (ry + dy)) * SX + (vx + dx)) * 2);
+        }
+        __builtin_memcpy(&bv, w4, 16);
+      } else {
+        // k = 8 grp + j: tap 2 s + grp / 2, channel 8 (grp & 1) + j
+        int tap = 2 * s + (grp >> 1);
+        if (tap > 26) tap = 13;
+        const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
+        const int sv = ((rz + dz) * SY + (ry + dy)) * SX + (vx + dx);
+        bv = *(const bf16x8*)(st + sv * 16 + (grp & 1) * 8);
+      }
+      return bv;
+    };
+    auto epilogue = [&](int row, const f32x4& acc) {
+      const int ry = row % CTY, rz = row / CTY;
+      // D layout: acc[r] = Out[channel 4*grp + r][voxel vx]
+      const int gx = x0 + vx, gy = y0 + ry, gz = z0 + rz;
+      if (gx < g.nx && gy < g.ny && gz < g.nz) {
+        const int64_t vi = (int64_t)gz * plane + (int64_t)gy * g.nx + gx;
+        if (EPI == EPI_GELU) {
+          float z[4];
+#pragma unroll
+          for (int r = 0; r < 4; ++r) z[r] = acc[r] + bz[r];
+          if (zout) *(float4*)(zout + vi * 16 + c0) = make_float4(z[0], z[1], z[2], z[3]);
+          uint2 packed;
+          packed.x = (uint32_t)f32_to_bf16(gelu_f(z[0])) | ((uint32_t)f32_to_bf16(gelu_f(z[1])) << 16);
+          packed.y = (uint32_t)f32_to_bf16(gelu_f(z[2])) | ((uint32_t)f32_to_bf16(gelu_f(z[3])) << 16);
+          *(uint2*)(yout + vi * 16 + c0) = packed;
+        } else if (EPI == EPI_LINEAR) {
+          if (grp == 0) fout[vi] = (float)(((double)acc[0] + (double)bz[0]) * scale[0]);
+        } else if (EPI == EPI_BWD) {
+          const float4 zp = *(const float4*)(zprev + vi * 16 + c0);
+          uint2 packed;
+          packed.x = (uint32_t)f32_to_bf16(acc[0] * gelu_grad_f(zp.x)) |
+                     ((uint32_t)f32_to_bf16(acc[1] * gelu_grad_f(zp.y)) << 16);
+          packed.y = (uint32_t)f32_to_bf16(acc[2] * gelu_grad_f(zp.z)) |
+                     ((uint32_t)f32_to_bf16(acc[3] * gelu_grad_f(zp.w)) << 16);
+          *(uint2*)(yout + vi * 16 + c0) = packed;
+        } else {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (c0 + r < COS) fout[vi * COS + c0 + r] = acc[r] + bz[r];
+        }
+      }
+    };
+    // each wave: rows (y, z) of the tile, 16 voxels along x per row
+    for (int row = wave; row < CTY * CTZ; row += 4) {
+      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < STEPS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s], bop(row, s), acc, 0, 0, 0);
+      epilogue(row, acc);
     }
   }
 }
@@ -378,6 +411,49 @@ __global__ __launch_bounds__(256) void smooth_axis(const float* __restrict__ src
   }
 }
 
+// One full pass B = Bx By Bz of the binomial low-pass on a 32 x 8 x 8 output tile staged with a
+// one-voxel halo in LDS (the three separable passes share the tile).
+constexpr int SMX = 32, SMY = 8, SMZ = 8;
+__global__ __launch_bounds__(256) void smooth3(const float* __restrict__ src, float* __restrict__ dst, Grid3 g) {
+  __shared__ float t0[SMZ + 2][SMY + 2][SMX + 2];
+  __shared__ float t1[SMZ + 2][SMY + 2][SMX];
+  __shared__ float t2[SMZ + 2][SMY][SMX];
+  const int tid = threadIdx.x;
+  const int tx = (g.nx + SMX - 1) / SMX, ty = (g.ny + SMY - 1) / SMY;
+  const int b = blockIdx.x;
+  const int x0 = (b % tx) * SMX, y0 = ((b / tx) % ty) * SMY, z0 = (b / (tx * ty)) * SMZ;
+  const int64_t plane = (int64_t)g.nx * g.ny;
+  for (int v = tid; v < (SMZ + 2) * (SMY + 2) * (SMX + 2); v += 256) {
+    const int sx = v % (SMX + 2), sy = (v / (SMX + 2)) % (SMY + 2), sz = v / ((SMX + 2) * (SMY + 2));
+    int gx = x0 + sx - 1, gy = y0 + sy - 1, gz = z0 + sz - 1;
+    bool ok = true;
+    if (g.periodic) {
+      gx = (gx + g.nx) % g.nx; gy = (gy + g.ny) % g.ny; gz = (gz + g.nz) % g.nz;
+    } else {
+      ok = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
+    }
+    t0[sz][sy][sx] = ok ? src[(int64_t)gz * plane + (int64_t)gy * g.nx + gx] : 0.f;
+  }
+  __syncthreads();
+  for (int v = tid; v < (SMZ + 2) * (SMY + 2) * SMX; v += 256) {
+    const int x = v % SMX, y = (v / SMX) % (SMY + 2), z = v / (SMX * (SMY + 2));
+    t1[z][y][x] = 0.25f * t0[z][y][x] + 0.5f * t0[z][y][x + 1] + 0.25f * t0[z][y][x + 2];
+  }
+  __syncthreads();
+  for (int v = tid; v < (SMZ + 2) * SMY * SMX; v += 256) {
+    const int x = v % SMX, y = (v / SMX) % SMY, z = v / (SMX * SMY);
+    t2[z][y][x] = 0.25f * t1[z][y][x] + 0.5f * t1[z][y + 1][x] + 0.25f * t1[z][y + 2][x];
+  }
+  __syncthreads();
+  for (int v = tid; v < SMZ * SMY * SMX; v += 256) {
+    const int x = v % SMX, y = (v / SMX) % SMY, z = v / (SMX * SMY);
+    const int gx = x0 + x, gy = y0 + y, gz = z0 + z;
+    if (gx < g.nx && gy < g.ny && gz < g.nz)
+      dst[(int64_t)gz * plane + (int64_t)gy * g.nx + gx] =
+          0.25f * t2[z][y][x] + 0.5f * t2[z + 1][y][x] + 0.25f * t2[z + 2][y][x];
+  }
+}
+
 __global__ __launch_bounds__(256) void f32_to_bf16_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst,
                                                           int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
@@ -420,13 +496,19 @@ __global__ __launch_bounds__(64) void pack_weights(const float* __restrict__ w, 
   const float* W = w + woff(l);
   const int mrow = lane & 15, grp = lane >> 4;
   for (int s = 0; s < NSTEP; ++s) {
-    const int tap = 2 * s + (grp >> 1);
     for (int j = 0; j < 8; ++j) {
-      const int kc = (grp & 1) * 8 + j;
       float val = 0.f;
-      if (tap < 27 && mrow < m_n && kc < ci_n) {
-        if (!flip) val = W[(mrow * CIN[l] + kc) * 27 + tap];
-        else val = W[(kc * CIN[l] + mrow) * 27 + (26 - tap)];
+      if (!flip && ci_n == 2) {
+        // two-channel layout: k = 8 grp + j -> tap 16 s + 4 grp + j/2, channel j % 2 (2 steps)
+        const int tap = 16 * s + 4 * grp + (j >> 1), kc = j & 1;
+        if (s < 2 && tap < 27 && mrow < m_n) val = W[(mrow * CIN[l] + kc) * 27 + tap];
+      } else {
+        const int tap = 2 * s + (grp >> 1);
+        const int kc = (grp & 1) * 8 + j;
+        if (tap < 27 && mrow < m_n && kc < ci_n) {
+          if (!flip) val = W[(mrow * CIN[l] + kc) * 27 + tap];
+          else val = W[(kc * CIN[l] + mrow) * 27 + (26 - tap)];
+        }
       }
       out[(s * 64 + lane) * 8 + j] = f32_to_bf16(val);
     }
@@ -623,8 +705,10 @@ static int check_grid(const tbs_net* n, const int64_t grid[3]) {
   return TBS_OK;
 }
 
+// persistent grid: enough workgroups to fill the 256 CUs several times, each looping over tiles
 static int conv_blocks(const int64_t grid[3]) {
-  return (int)(((grid[0] + CTX - 1) / CTX) * ((grid[1] + CTY - 1) / CTY) * ((grid[2] + CTZ - 1) / CTZ));
+  const int64_t tiles = ((grid[0] + CTX - 1) / CTX) * ((grid[1] + CTY - 1) / CTY) * ((grid[2] + CTZ - 1) / CTZ);
+  return (int)std::min<int64_t>(tiles, 2048);
 }
 
 static int smooth(tbs_net* n, float* buf, float* tmp, Grid3 g);
@@ -656,13 +740,14 @@ static int forward_layers(tbs_net* n, Grid3 g, int keep) {
 static int smooth(tbs_net* n, float* buf, float* tmp, Grid3 g) {
   const int64_t N = (int64_t)g.nx * g.ny * g.nz;
   int blocks = (int)std::min<int64_t>((N + 255) / 256, 8192);
+  (void)blocks;
+  const int sblocks = ((g.nx + SMX - 1) / SMX) * ((g.ny + SMY - 1) / SMY) * ((g.nz + SMZ - 1) / SMZ);
   float* a = buf;
   float* b = tmp;
-  for (int p = 0; p < SMOOTH_PASSES; ++p)
-    for (int ax = 0; ax < 3; ++ax) {
-      hipLaunchKernelGGL(smooth_axis, dim3(blocks), dim3(256), 0, n->st, (const float*)a, b, g, ax);
-      float* t = a; a = b; b = t;
-    }
+  for (int p = 0; p < SMOOTH_PASSES; ++p) {
+    hipLaunchKernelGGL(smooth3, dim3(sblocks), dim3(256), 0, n->st, (const float*)a, b, g);
+    float* t = a; a = b; b = t;
+  }
   if (a != buf) NCHK(hipMemcpyAsync(buf, a, (size_t)N * 4, hipMemcpyDeviceToDevice, n->st));
   NCHK(hipGetLastError());
   return TBS_OK;

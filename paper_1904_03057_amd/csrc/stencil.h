@@ -5,11 +5,26 @@
 #ifndef STENCIL_TY
 #define STENCIL_TY 16
 #endif
+#ifndef STENCIL_APPLY_WX
+#define STENCIL_APPLY_WX 1
+#endif
+
+#ifndef STENCIL_CG_TY
+#define STENCIL_CG_TY 16
+#endif
 
 namespace tbs {
 
 constexpr int kTileX = 64;
-constexpr int kTileY = STENCIL_TY;
+constexpr int kTileY = STENCIL_TY;  // smallest tile height: sizes the partial-sum buffers
+
+// Tile height per (mode, compute precision): taller tiles re-read fewer halo rows; the FP64
+// kernels keep 16 rows for register room.
+constexpr int stencil_tile_y(int mode, int compute_bytes) {
+  return compute_bytes == 4 ? ((mode == M_APPLY) ? 32 : (mode == M_CG1 ? STENCIL_CG_TY : 16)) : 16;
+}
+// Number of workgroups (= partial sums written) of a stencil launch of this mode.
+int stencil_blocks(const StencilArgs& a, int mode, int compute_bytes);
 
 // stencil.hip
 hipError_t launch_apply(const StencilArgs& a, int n, int bc, int in_dt, int out_dt, hipStream_t st);

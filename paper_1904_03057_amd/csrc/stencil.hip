@@ -9,7 +9,7 @@
 // which expands to (Mx My Mz + ax Kx My Mz + ay Mx Ky Mz + az Mx My Kz) u.  Symmetric taps are
 // applied to pair sums (u_{i-j} + u_{i+j}), and every accumulation is an explicit FMA chain.
 //
-// Execution ("2.5-D" streaming): a 256-thread workgroup owns a 64 x TY tile of the x-y plane and
+// Execution ("2.5-D" streaming): a workgroup of WX x 256 threads owns a 64 WX x TY tile of the x-y plane and
 // marches along z through its chunk of planes.  Each input plane tile (halo n rows in y, halo HX
 // columns in x, HX = n rounded up to the 16-byte vector width) is fetched with 16-byte loads
 // one plane ahead into registers, converted/transformed and staged in LDS.  The x-pass (lanes =
@@ -34,12 +34,13 @@ template <> __device__ __forceinline__ double to_c<uint16_t, double>(uint16_t v)
 template <typename Ts, typename Tc> __device__ __forceinline__ Ts from_c(Tc v) { return (Ts)v; }
 template <> __device__ __forceinline__ uint16_t from_c<uint16_t, float>(float v) { return f32_to_bf16(v); }
 
-template <int N, int TY, int MODE, typename Tin, typename Tc, typename Tout, int BC, bool VEC>
-__global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
+template <int N, int TY, int MODE, typename Tin, typename Tc, typename Tout, int BC, bool VEC, int WX>
+__global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
+  constexpr int NT = 256 * WX;                     // threads: WX column groups of 64 x 4 waves
   constexpr int VE = VEC ? 16 / (int)sizeof(Tin) : 1;
   using Raw = VecN<Tin, VE>;   // staged input (u, u_prev, x, p_old)
   using RawC = VecN<Tc, VE>;   // companion compute-precision vectors (q of RHS; r and x of CG1)
-  constexpr int TX = 64;
+  constexpr int TX = 64 * WX;
   constexpr int HX = ((N + VE - 1) / VE) * VE;   // x-halo rounded to whole vectors
   constexpr int R = TY + 2 * N;                   // staged rows
   constexpr int C = TX + 2 * HX;                  // staged columns
@@ -47,8 +48,8 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
   constexpr int T = 2 * N + 1;                    // taps
   constexpr int CORE = TY * (TX / VE);            // vectors of the tile's own points
   constexpr int HALO = R * CV - CORE;              // halo vectors
-  constexpr int NVC = (CORE + 255) / 256;          // core vectors per thread (slots 0..NVC-1)
-  constexpr int NVH = (HALO + 255) / 256;          // halo vectors per thread
+  constexpr int NVC = (CORE + NT - 1) / NT;        // core vectors per thread (slots 0..NVC-1)
+  constexpr int NVH = (HALO + NT - 1) / NT;        // halo vectors per thread
   constexpr int NV = NVC + NVH;
   constexpr int RPW = TY / 4;                      // output rows per wave
   constexpr int QD = (MODE == M_CG1) ? N + 1 : 1;  // depth of the centre-value ring (CG1)
@@ -58,13 +59,15 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
   __shared__ Tc su[R * TX];
   __shared__ Tc sv[R * TX];
   __shared__ Tc cring[QD * TY * TX];  // p at the own points of the last n+1 planes (CG1 dot product)
-  __shared__ double red[2][4];
+  __shared__ double red[2][4 * WX];
 
   if (MODE == M_CG1 && a.scal->done) return;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
-  const int wave = tid >> 6;
+  const int wv = tid >> 6;
+  const int col = (wv % WX) * 64 + lane;           // tile column of this lane
+  const int wave = wv / WX;                        // row group 0..3
 
   const int bid = xcd_remap(blockIdx.x, a.nblocks);
   // logical tile order (x- or y-tiles fastest, then the other, then z-chunks): the tiles an XCD
@@ -105,12 +108,12 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
     int r = 0, cv = 0;
     bool present;
     if (v < NVC) {
-      const int idx = tid + 256 * v;
+      const int idx = tid + NT * v;
       present = idx < CORE;
       r = N + idx / (TX / VE);
       cv = HX / VE + idx % (TX / VE);
     } else {
-      int idx = tid + 256 * (v - NVC);
+      int idx = tid + NT * (v - NVC);
       present = idx < HALO;
       if (idx < 2 * N * CV) {
         const int rr = idx / CV;
@@ -238,7 +241,7 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
     for (int i = 0; i < RPW; ++i) acc[s][i] = (Tc)0;
 
   double part0 = 0.0, part1 = 0.0;
-  const int gxo = x0 + lane;
+  const int gxo = x0 + col;
   const bool colown = gxo < nx;
 
   const int kbeg = z0 - N, kend = z0 + zc_eff + N;
@@ -259,11 +262,11 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
           const int qs = ((k % QD) + QD) % QD;
 #pragma unroll
           for (int i = 0; i < RPW; ++i)
-            cring[(qs * TY + wave * RPW + i) * TX + lane] = stage[(wave * RPW + i + N) * C + lane + HX];
+            cring[(qs * TY + wave * RPW + i) * TX + col] = stage[(wave * RPW + i + N) * C + col + HX];
         }
         // x-pass over all R staged rows (rows dealt to the waves round-robin)
         for (int r = wave; r < R; r += 4) {
-          const Tc* row = stage + r * C + HX + lane;
+          const Tc* row = stage + r * C + HX + col;
           const Tc c0 = row[0];
           Tc U = m[0] * c0;
           Tc Vv = mx[0] * c0;
@@ -273,8 +276,8 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
             U = fmad(m[j], sm, U);
             Vv = fmad(mx[j], sm, Vv);
           }
-          su[r * TX + lane] = U;
-          sv[r * TX + lane] = Vv;
+          su[r * TX + col] = U;
+          sv[r * TX + col] = Vv;
         }
       }
       __syncthreads();
@@ -282,8 +285,8 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
         Tc uc[RPW + 2 * N], vc[RPW + 2 * N];
 #pragma unroll
         for (int j = 0; j < RPW + 2 * N; ++j) {
-          uc[j] = su[(wave * RPW + j) * TX + lane];
-          if (MODE != M_RHS) vc[j] = sv[(wave * RPW + j) * TX + lane];
+          uc[j] = su[(wave * RPW + j) * TX + col];
+          if (MODE != M_RHS) vc[j] = sv[(wave * RPW + j) * TX + col];
         }
 #pragma unroll
         for (int i = 0; i < RPW; ++i) {
@@ -333,7 +336,7 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
               } else if (MODE == M_CG1) {
                 if (a.nt_store) Io<Tout>::template st_nt<Tc>(a.out0, gi, val);
                 else Io<Tout>::template st<Tc>(a.out0, gi, val);
-                part0 = fma((double)cring[(qo * TY + wave * RPW + i) * TX + lane], (double)val, part0);
+                part0 = fma((double)cring[(qo * TY + wave * RPW + i) * TX + col], (double)val, part0);
               } else {
                 const double b = a.bvec[gi];
                 const double r = b - (double)val;
@@ -354,11 +357,14 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
   if (MODE == M_CG1 || MODE == M_RESID) {
     part0 = wave_sum(part0);
     part1 = wave_sum(part1);
-    if (lane == 0) { red[0][wave] = part0; red[1][wave] = part1; }
+    if (lane == 0) { red[0][wv] = part0; red[1][wv] = part1; }
     __syncthreads();
     if (tid == 0) {
-      a.part0[blockIdx.x] = ((red[0][0] + red[0][1]) + (red[0][2] + red[0][3]));
-      if (MODE == M_RESID) a.part1[blockIdx.x] = ((red[1][0] + red[1][1]) + (red[1][2] + red[1][3]));
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < 4 * WX; ++q) { s0 += red[0][q]; s1 += red[1][q]; }
+      a.part0[blockIdx.x] = s0;
+      if (MODE == M_RESID) a.part1[blockIdx.x] = s1;
     }
   }
 }
@@ -366,29 +372,33 @@ __global__ __launch_bounds__(256) void stencil_kernel(StencilArgs a) {
 // ------------------------------------------------------------------------------------------
 // host-side launch helpers
 
-// tile height per (mode, compute type): taller tiles cut the x-pass halo work of the
-// arithmetic-heavy FP32 apply; the CG and FP64 variants keep 16 rows for register room
-template <int MODE, typename Tc> constexpr int tile_y() {
-  return (MODE == M_APPLY && sizeof(Tc) == 4) ? 32 : 16;
+// Tile shape per (mode, compute type): the arithmetic-heavy FP32 apply uses 128 x 32 tiles
+// (512 threads: the x halo costs fewer partial cache lines per row); the kernels that write
+// per-block partial sums keep 64 x 16 tiles (the host sizes their partial-sum buffers for it).
+template <int MODE, typename Tc> constexpr int tile_y() { return stencil_tile_y(MODE, (int)sizeof(Tc)); }
+template <int MODE, typename Tc> constexpr int tile_wx() {
+  return (MODE == M_APPLY && sizeof(Tc) == 4) ? STENCIL_APPLY_WX : 1;
 }
 
 template <int N, int MODE, typename Tin, typename Tc, typename Tout>
 static hipError_t launch_bc(const StencilArgs& a0, int bc, bool vec, hipStream_t st) {
   constexpr int TY = tile_y<MODE, Tc>();
-  StencilArgs a = a0;  // geometry for this tile height
+  constexpr int WX = tile_wx<MODE, Tc>();
+  StencilArgs a = a0;  // geometry for this tile shape
+  a.tiles_x = (a.nx + 64 * WX - 1) / (64 * WX);
   a.tiles_y = (a.ny + TY - 1) / TY;
   a.nblocks = a.tiles_x * a.tiles_y * a.nchunks;
-  dim3 grid(a.nblocks), block(256);
+  dim3 grid(a.nblocks), block(256 * WX);
   if (vec) {
     if (bc == BC_PERIODIC)
-      hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC_PERIODIC, true>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC_PERIODIC, true, WX>), grid, block, 0, st, a);
     else
-      hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC_DIRICHLET, true>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC_DIRICHLET, true, WX>), grid, block, 0, st, a);
   } else {
     if (bc == BC_PERIODIC)
-      hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC_PERIODIC, false>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC_PERIODIC, false, WX>), grid, block, 0, st, a);
     else
-      hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC_DIRICHLET, false>), grid, block, 0, st, a);
+      hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC_DIRICHLET, false, WX>), grid, block, 0, st, a);
   }
   return hipGetLastError();
 }
@@ -408,8 +418,10 @@ static hipError_t launch_n(const StencilArgs& a, int n, int bc, hipStream_t st) 
   return hipErrorInvalidValue;
 }
 
-int stencil_tile_y(int mode, int compute_bytes) {
-  return (mode == M_APPLY && compute_bytes == 4) ? 32 : 16;
+int stencil_blocks(const StencilArgs& a, int mode, int compute_bytes) {
+  const int ty = stencil_tile_y(mode, compute_bytes);
+  const int wx = (mode == M_APPLY && compute_bytes == 4) ? STENCIL_APPLY_WX : 1;
+  return ((a.nx + 64 * wx - 1) / (64 * wx)) * ((a.ny + ty - 1) / ty) * a.nchunks;
 }
 
 // dtype codes: 0 = f64, 1 = f32, 2 = bf16
