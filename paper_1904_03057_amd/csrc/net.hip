@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstring>
 #include <new>
+#include <type_traits>
 
 #include "../../include/tbs.h"
 #include "common.h"
@@ -30,7 +31,7 @@ namespace net {
 constexpr int NL = 4;
 constexpr int CIN[NL] = {2, 16, 16, 16};
 constexpr int COUT[NL] = {16, 16, 16, 1};
-constexpr int NSTEP = 14;         // MFMA K-steps: 28 taps (27 + one zero) / 2
+constexpr int NSTEP = 15;         // MFMA K-steps of the 16-channel layout (27 taps + 3 zero partners) / 2
 constexpr int PACK = NSTEP * 64 * 8;  // bf16 per packed layer
 constexpr int WG_PARTS = 6928;    // max partial-gradient row: 16*16*27 weights + 16 biases
 constexpr int SMOOTH_PASSES = 2;  // passes of the separable binomial low-pass after the last layer
@@ -44,7 +45,22 @@ static_assert(woff(NL) == TBS_NET_PARAMS, "parameter count");
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
-__device__ __forceinline__ float gelu_f(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// GELU(x) = x Phi(x) = max(x, 0) - |x| Phi(-|x|), with the normal tail Phi(-y) = t 2^(P(t) - y^2 /
+// (2 ln 2)), t = 1 / (1 + c y), P of degree 6 fitted by fit_gelu.py (relative error of Phi(-y)
+// below 1.3e-6 for all y >= 0), so the negative tail keeps its relative accuracy.
+__device__ __forceinline__ float gelu_f(float x) {
+  const float y = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(fmaf(2.700000107e-01f, y, 1.0f));
+  float p = 3.957020044e-01f;
+  p = fmaf(p, t, -1.359942675e+00f);
+  p = fmaf(p, t, 1.348554134e+00f);
+  p = fmaf(p, t, -3.906427920e-01f);
+  p = fmaf(p, t, 8.047851324e-01f);
+  p = fmaf(p, t, 1.414555073e+00f);
+  p = fmaf(p, t, -3.213009119e+00f);
+  const float q = t * __builtin_amdgcn_exp2f(fmaf(y * y, -0.72134752044448170f, p));  // Phi(-y)
+  return fmaf(-y, q, fmaxf(x, 0.f));
+}
 __device__ __forceinline__ float gelu_grad_f(float x) {
   return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
 }
@@ -59,9 +75,46 @@ struct Grid3 {
 
 enum Epi { EPI_GELU = 0, EPI_LINEAR = 1, EPI_BWD = 2, EPI_RAW = 3 };
 
-constexpr int CTX = 16, CTY = 8, CTZ = 4;             // output tile (x, y, z)
-constexpr int SX = CTX + 2, SY = CTY + 2, SZ = CTZ + 2;  // staged tile
-constexpr int SVOX = SX * SY * SZ;
+// Geometry of the z-marching convolution: a workgroup owns a 32 x 8 column of output voxels and
+// marches through a chunk of zc planes, keeping the three input planes a output plane needs in an
+// LDS ring (one-voxel halo in x and y) and fetching the next plane into registers meanwhile.
+constexpr int CTX = 32, CTY = 8;                  // output tile per plane (x, y)
+constexpr int SX = CTX + 2, SY = CTY + 2;          // staged plane
+constexpr int PLV = SX * SY;                       // voxels per staged plane
+constexpr int WROWS = 2 * CTY / 4;                 // 16-voxel rows per wave per plane
+
+struct ConvGeo {
+  int tx, ty, nch, zc;
+};
+// z-chunk length: about 2048 workgroups in flight on small grids, at most 96 planes per chunk
+__host__ __device__ inline ConvGeo conv_geo(const Grid3& g) {
+  ConvGeo c;
+  c.tx = (g.nx + CTX - 1) / CTX;
+  c.ty = (g.ny + CTY - 1) / CTY;
+  int64_t zc = (int64_t)g.nz * c.tx * c.ty / 2048;
+  c.zc = (int)(zc < 4 ? 4 : (zc > 96 ? 96 : zc));
+  c.nch = (g.nz + c.zc - 1) / c.zc;
+  return c;
+}
+
+// 16-channel K order.  Tap index t = 9 dz + 3 dy + dx.  K-step s holds taps tap16(s, 0) and
+// tap16(s, 1): steps 3 dy + dx pair (0, dy, dx) with (1, dy, dx); steps 9 + dy pair (2, dy, 0) with
+// (2, dy, 1); steps 12 + dy hold (2, dy, 2) and a zero-weight partner.  For a fixed dz-pair and dx
+// the B operand depends only on the staged row y + dy, so one LDS read serves the three output
+// rows it touches (dy = 0, 1, 2), each with its own A operand.
+__host__ __device__ constexpr int tap16(int s, int half) {
+  return s < 9 ? s + 9 * half : (s < 12 ? 18 + 3 * (s - 9) + half : 18 + 3 * (s - 12) + 2);
+}
+__host__ __device__ constexpr bool pad16(int s, int half) { return s >= 12 && half == 1; }
+
+typedef __attribute__((__vector_size__(2 * sizeof(__bf16)))) __bf16 bf16x2;
+// two floats to packed bf16 (round to nearest even) with the gfx950 conversion instruction
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+  bf16x2 v;
+  v[0] = (__bf16)lo;
+  v[1] = (__bf16)hi;
+  return __builtin_bit_cast(uint32_t, v);
+}
 
 // in: [voxel][CIS] bf16; wpk: packed A operands [steps][64 lanes][8]; out per epilogue:
 //   EPI_GELU:   zout (f32 [voxel][16], nullable) = acc + bias; yout (bf16 [voxel][16]) = GELU(z)
@@ -69,9 +122,10 @@ constexpr int SVOX = SX * SY * SZ;
 //   EPI_BWD:    yout (bf16 [voxel][16]) = acc * GELU'(zprev[voxel][c])       (backward data)
 //   EPI_RAW:    fout (f32 [voxel][COS]) = acc (+ bias if bias != NULL)       (parity probes)
 // Two K layouts: with 16 (or zero-padded 1) input channels each K-step holds 2 taps x 16
-// channels (14 steps); with 2 input channels it holds 16 taps x 2 channels (2 steps, 27 taps
-// padded to 32), and the tile keeps only the 2 channels in LDS.  Workgroups are persistent:
-// they load the weights once and loop over tiles.
+// channels (15 steps, order tap16); with 2 input channels it holds 16 taps x 2 channels (2 steps,
+// 27 taps padded to 32), and the ring keeps only the 2 channels.  Each wave owns 4 consecutive
+// rows (y) of 16 voxels (x) per plane; the plane loop is unrolled by the ring period so all LDS
+// reads of the B operands use immediate offsets.
 template <int CIS, int COS, int EPI>
 __global__ __launch_bounds__(256) void conv_mfma(const uint16_t* __restrict__ in, const uint16_t* __restrict__ wpk,
                                                  const float* __restrict__ bias, Grid3 g,
@@ -80,12 +134,19 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t* __restrict__ in
                                                  const double* __restrict__ scale) {
   constexpr bool TWO = (CIS == 2);
   constexpr int STEPS = TWO ? 2 : NSTEP;
-  constexpr int VW = TWO ? 2 : 16;     // bf16 per staged voxel
-  __shared__ __attribute__((aligned(16))) uint16_t st[SVOX * VW];
+  constexpr int VW = TWO ? 2 : 16;                  // bf16 per staged voxel
+  constexpr int UNITS = CIS == 16 ? 2 * PLV : PLV;  // load units per plane (16 B, or one voxel)
+  constexpr int UPT = (UNITS + 255) / 256;          // units per thread
+  using Unit = typename std::conditional<CIS == 16, uint4, typename std::conditional<TWO, uint32_t, uint16_t>::type>::type;
+  __shared__ __attribute__((aligned(16))) uint16_t st[3 * PLV * VW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int tx = (g.nx + CTX - 1) / CTX, ty = (g.ny + CTY - 1) / CTY, tz = (g.nz + CTZ - 1) / CTZ;
-  const int ntiles = tx * ty * tz;
+  const ConvGeo geo = conv_geo(g);
   const int64_t plane = (int64_t)g.nx * g.ny;
+
+  const int bid = xcd_remap(blockIdx.x, gridDim.x);
+  const int bx = bid % geo.tx, by = (bid / geo.tx) % geo.ty, ch = bid / (geo.tx * geo.ty);
+  const int x0 = bx * CTX, y0 = by * CTY, z0 = ch * geo.zc;
+  const int zc = min(geo.zc, g.nz - z0);
 
   // A operands (weights) for all K-steps, loaded once and kept in registers
   bf16x8 wa[STEPS];
@@ -99,103 +160,171 @@ __global__ __launch_bounds__(256) void conv_mfma(const uint16_t* __restrict__ in
 #pragma unroll
     for (int r = 0; r < 4; ++r) bz[r] = (c0 + r < COS) ? bias[c0 + r] : 0.f;
 
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-    const int bx = tile % tx, by = (tile / tx) % ty, bzt = tile / (tx * ty);
-    const int x0 = bx * CTX, y0 = by * CTY, z0 = bzt * CTZ;
-    __syncthreads();  // previous tile's reads of st are done
-    for (int v = tid; v < SVOX; v += 256) {
-      const int sx = v % SX, sy = (v / SX) % SY, sz = v / (SX * SY);
-      int gx = x0 + sx - 1, gy = y0 + sy - 1, gz = z0 + sz - 1;
-      bool ok = true;
-      if (g.periodic) {
-        gx = (gx + g.nx) % g.nx; gy = (gy + g.ny) % g.ny; gz = (gz + g.nz) % g.nz;
-      } else {
-        ok = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
-      }
-      const int64_t vi = (int64_t)gz * plane + (int64_t)gy * g.nx + gx;
-      if (TWO) {
-        *(uint32_t*)(st + v * 2) = ok ? *(const uint32_t*)(in + vi * 2) : 0u;
-      } else {
-        uint4 lo = make_uint4(0, 0, 0, 0), hi = make_uint4(0, 0, 0, 0);
-        if (ok) {
-          if (CIS == 16) {
-            const uint4* p = (const uint4*)(in + vi * 16);
-            lo = p[0];
-            hi = p[1];
-          } else {
-            lo.x = in[vi];
-          }
-        }
-        uint4* d = (uint4*)(st + v * 16);
-        d[0] = lo;
-        d[1] = hi;
+  // this thread's load units: plane-relative global voxel offsets (-1: outside a Dirichlet grid)
+  int uoff[UPT];
+#pragma unroll
+  for (int q = 0; q < UPT; ++q) {
+    const int u = tid + 256 * q;
+    const int v = CIS == 16 ? (u >> 1) : u;
+    int gx = x0 - 1 + v % SX, gy = y0 - 1 + v / SX;
+    bool ok = u < UNITS;
+    if (g.periodic) {
+      gx = (gx + g.nx) % g.nx;
+      gy = (gy + g.ny) % g.ny;
+    } else {
+      ok = ok && gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny;
+    }
+    uoff[q] = ok ? gy * g.nx + gx : -1;
+  }
+  if (CIS == 1) {  // channels 1..15 of the ring stay zero
+    for (int i = tid; i < 3 * PLV * VW / 8; i += 256) ((uint4*)st)[i] = make_uint4(0, 0, 0, 0);
+    __syncthreads();
+  }
+  Unit pre[UPT];
+  // fetch relative plane j (global plane z0 - 1 + j) into pre
+  auto fetch = [&](int j) {
+    int gz = z0 - 1 + j;
+    bool pv = true;
+    if (g.periodic) gz = (gz + g.nz) % g.nz;
+    else pv = gz >= 0 && gz < g.nz;
+    const int64_t pb = (int64_t)gz * plane;
+#pragma unroll
+    for (int q = 0; q < UPT; ++q) {
+      pre[q] = Unit{};
+      if (pv && uoff[q] >= 0) {
+        if constexpr (CIS == 16) pre[q] = ((const uint4*)(in + (pb + uoff[q]) * 16))[(tid + 256 * q) & 1];
+        else if constexpr (TWO) pre[q] = *(const uint32_t*)(in + (pb + uoff[q]) * 2);
+        else pre[q] = in[pb + uoff[q]];
       }
     }
-    __syncthreads();
+  };
+  auto stash = [&](int slot) {
+#pragma unroll
+    for (int q = 0; q < UPT; ++q) {
+      const int u = tid + 256 * q;
+      if (UNITS % 256 == 0 || u < UNITS) {
+        if constexpr (CIS == 16) ((uint4*)st)[slot * PLV * 2 + u] = pre[q];
+        else if constexpr (TWO) ((uint32_t*)st)[slot * PLV + u] = pre[q];
+        else st[(slot * PLV + u) * 16] = pre[q];
+      }
+    }
+  };
 
-    // B operand of K-step s for tile row `row` (16 voxels along x)
-    auto bop = [&](int row, int s) -> bf16x8 {
-      const int ry = row % CTY, rz = row / CTY;
-      bf16x8 bv;
-      if (TWO) {
-        // k = 8 grp + j: tap 16 s + 4 grp + j/2, channel j % 2
-        uint32_t w4[4];
+  // B operand lane offsets (bf16 elements of st) for the wave's first row: wave w owns rows
+  // y = 4 (w >> 1) + r (r = 0..3) of x half w & 1
+  const int yb = 4 * (wave >> 1), xh = wave & 1;
+  const int lb = yb * SX + xh * 16 + vx;
+  int loff[TWO ? 24 : 5];
+  if (TWO) {
+    // k = 8 grp + j: tap 16 s + 4 grp + j/2, channel j % 2; padding taps (> 26) read tap 13
+#pragma unroll
+    for (int ph = 0; ph < 3; ++ph)
+#pragma unroll
+      for (int s = 0; s < 2; ++s)
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
           int tap = 16 * s + 4 * grp + t;
-          if (tap > 26) tap = 13;  // padding taps: zero weights, finite data
-          const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
-          w4[t] = *(const uint32_t*)(st + (((rz + dz) * SY + (ry + dy)) * SX + (vx + dx)) * 2);
+          if (tap > 26) tap = 13;
+          loff[8 * ph + 4 * s + t] = (lb + ((ph + tap / 9) % 3) * PLV + ((tap / 3) % 3) * SX + tap % 3) * 2;
         }
-        __builtin_memcpy(&bv, w4, 16);
-      } else {
-        // k = 8 grp + j: tap 2 s + grp / 2, channel 8 (grp & 1) + j
-        int tap = 2 * s + (grp >> 1);
-        if (tap > 26) tap = 13;
-        const int dx = tap % 3, dy = (tap / 3) % 3, dz = tap / 9;
-        const int sv = ((rz + dz) * SY + (ry + dy)) * SX + (vx + dx);
-        bv = *(const bf16x8*)(st + sv * 16 + (grp & 1) * 8);
-      }
-      return bv;
-    };
-    auto epilogue = [&](int row, const f32x4& acc) {
-      const int ry = row % CTY, rz = row / CTY;
-      // D layout: acc[r] = Out[channel 4*grp + r][voxel vx]
-      const int gx = x0 + vx, gy = y0 + ry, gz = z0 + rz;
-      if (gx < g.nx && gy < g.ny && gz < g.nz) {
-        const int64_t vi = (int64_t)gz * plane + (int64_t)gy * g.nx + gx;
-        if (EPI == EPI_GELU) {
-          float z[4];
+  } else {
+    // k = 8 grp + j: tap tap16(s, grp >> 1), channel 8 (grp & 1) + j
+    const int l0 = lb * 16 + (grp & 1) * 8, h = grp >> 1;
 #pragma unroll
-          for (int r = 0; r < 4; ++r) z[r] = acc[r] + bz[r];
-          if (zout) *(float4*)(zout + vi * 16 + c0) = make_float4(z[0], z[1], z[2], z[3]);
-          uint2 packed;
-          packed.x = (uint32_t)f32_to_bf16(gelu_f(z[0])) | ((uint32_t)f32_to_bf16(gelu_f(z[1])) << 16);
-          packed.y = (uint32_t)f32_to_bf16(gelu_f(z[2])) | ((uint32_t)f32_to_bf16(gelu_f(z[3])) << 16);
-          *(uint2*)(yout + vi * 16 + c0) = packed;
-        } else if (EPI == EPI_LINEAR) {
-          if (grp == 0) fout[vi] = (float)(((double)acc[0] + (double)bz[0]) * scale[0]);
-        } else if (EPI == EPI_BWD) {
-          const float4 zp = *(const float4*)(zprev + vi * 16 + c0);
-          uint2 packed;
-          packed.x = (uint32_t)f32_to_bf16(acc[0] * gelu_grad_f(zp.x)) |
-                     ((uint32_t)f32_to_bf16(acc[1] * gelu_grad_f(zp.y)) << 16);
-          packed.y = (uint32_t)f32_to_bf16(acc[2] * gelu_grad_f(zp.z)) |
-                     ((uint32_t)f32_to_bf16(acc[3] * gelu_grad_f(zp.w)) << 16);
-          *(uint2*)(yout + vi * 16 + c0) = packed;
+    for (int ph = 0; ph < 3; ++ph) loff[ph] = l0 + h * ((ph == 2 ? -2 : 1) * PLV * 16);  // dz 0 -> dz 1
+    loff[3] = l0 + h * 16;                                                           // dx 0 -> dx 1
+    loff[4] = l0;                                                                    // partner unused
+  }
+
+  // prologue: ring slots 0..2 hold planes z0-1, z0, z0+1; registers hold plane z0+2
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    fetch(j);
+    stash(j);
+  }
+  fetch(3);
+
+  for (int i0 = 0; i0 < zc; i0 += 3) {
+#pragma unroll
+    for (int ph = 0; ph < 3; ++ph) {
+      const int i = i0 + ph;
+      if (i < zc) {  // uniform
+        __syncthreads();  // plane z0 + i + 1 is in the ring
+        const int gz = z0 + i;
+        f32x4 acc[WROWS];
+#pragma unroll
+        for (int r = 0; r < WROWS; ++r) acc[r] = f32x4{0.f, 0.f, 0.f, 0.f};
+        if constexpr (TWO) {
+#pragma unroll
+          for (int r = 0; r < WROWS; ++r)
+#pragma unroll
+            for (int s = 0; s < STEPS; ++s) {
+              uint32_t w4[4];
+#pragma unroll
+              for (int t = 0; t < 4; ++t) w4[t] = *(const uint32_t*)(st + loff[8 * ph + 4 * s + t] + r * SX * 2);
+              bf16x8 bv;
+              __builtin_memcpy(&bv, w4, 16);
+              acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s], bv, acc[r], 0, 0, 0);
+            }
         } else {
+          // staged rows yb + yy, yy = 0..5, feed output rows r = yy - dy
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (c0 + r < COS) fout[vi * COS + c0 + r] = acc[r] + bz[r];
+          for (int yy = 0; yy < WROWS + 2; ++yy) {
+#pragma unroll
+            for (int q = 0; q < 5; ++q) {
+              // q < 3: planes (k-1, k) at dx = q; q = 3: plane k+1 at dx (0, 1); q = 4: plane k+1 at dx 2
+              const int pl = q < 3 ? ph : (ph + 2) % 3;
+              const int dx = q < 3 ? q : (q == 3 ? 0 : 2);
+              const int lo = q < 3 ? loff[ph] : loff[q];
+              const bf16x8 bv = *(const bf16x8*)(st + lo + (pl * PLV + yy * SX + dx) * 16);
+#pragma unroll
+              for (int dy = 0; dy < 3; ++dy) {
+                const int r = yy - dy;
+                if (r >= 0 && r < WROWS) {
+                  const int sidx = q < 3 ? 3 * dy + q : (q == 3 ? 9 + dy : 12 + dy);
+                  acc[r] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[sidx], bv, acc[r], 0, 0, 0);
+                }
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < WROWS; ++r) {
+          // D layout: acc[r] = Out[channel 4 grp + r][voxel vx]
+          const f32x4 A = acc[r];
+          const int gx = x0 + xh * 16 + vx, gy = y0 + yb + r;
+          if (gx < g.nx && gy < g.ny) {
+            const int64_t vi = (int64_t)gz * plane + (int64_t)gy * g.nx + gx;
+            if (EPI == EPI_GELU) {
+              float z[4];
+#pragma unroll
+              for (int c = 0; c < 4; ++c) z[c] = A[c] + bz[c];
+              if (zout) *(float4*)(zout + vi * 16 + c0) = make_float4(z[0], z[1], z[2], z[3]);
+              uint2 packed;
+              packed.x = pack_bf16x2(gelu_f(z[0]), gelu_f(z[1]));
+              packed.y = pack_bf16x2(gelu_f(z[2]), gelu_f(z[3]));
+              *(uint2*)(yout + vi * 16 + c0) = packed;
+            } else if (EPI == EPI_LINEAR) {
+              if (grp == 0) fout[vi] = (float)(((double)A[0] + (double)bz[0]) * scale[0]);
+            } else if (EPI == EPI_BWD) {
+              const float4 zp = *(const float4*)(zprev + vi * 16 + c0);
+              uint2 packed;
+              packed.x = pack_bf16x2(A[0] * gelu_grad_f(zp.x), A[1] * gelu_grad_f(zp.y));
+              packed.y = pack_bf16x2(A[2] * gelu_grad_f(zp.z), A[3] * gelu_grad_f(zp.w));
+              *(uint2*)(yout + vi * 16 + c0) = packed;
+            } else {
+#pragma unroll
+              for (int c = 0; c < 4; ++c)
+                if (c0 + c < COS) fout[vi * COS + c0 + c] = A[c] + bz[c];
+            }
+          }
+        }
+        __syncthreads();  // every wave is done with slot ph (plane z0 + i - 1)
+        if (i + 3 <= zc + 1) {
+          stash(ph);                         // plane z0 + i + 2 (relative plane i + 3)
+          if (i + 4 <= zc + 1) fetch(i + 4);
         }
       }
-    };
-    // each wave: rows (y, z) of the tile, 16 voxels along x per row
-    for (int row = wave; row < CTY * CTZ; row += 4) {
-      f32x4 acc = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int s = 0; s < STEPS; ++s) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[s], bop(row, s), acc, 0, 0, 0);
-      epilogue(row, acc);
     }
   }
 }
@@ -484,8 +613,8 @@ __global__ __launch_bounds__(256) void adam(float* __restrict__ w, float* __rest
   w[i] = w[i] - lr * mh / (sqrtf(vh) + eps);
 }
 
-// Packed A operands of layer l.  Forward: A[m][k] = W[m][ci][tap] with tap = 2s + (k >> 4),
-// ci = k & 15 (zero outside the layer's channels and for tap 27).  Backward data (flip = 1):
+// Packed A operands of layer l.  Forward: A[m][k] = W[m][ci][tap] with tap = tap16(s, k >> 4),
+// ci = k & 15 (zero outside the layer's channels and for the padding partners of steps 12-14).  Backward data (flip = 1):
 // the transposed convolution's weights W'[ci][co][tap] = W[co][ci][26 - tap], M = ci, K = (tap, co).
 // Lane layout of v_mfma_f32_16x16x32_bf16 A: lane holds row (lane & 15), k = 8 (lane >> 4) + j.
 __global__ __launch_bounds__(64) void pack_weights(const float* __restrict__ w, int l, int flip,
@@ -503,9 +632,10 @@ __global__ __launch_bounds__(64) void pack_weights(const float* __restrict__ w, 
         const int tap = 16 * s + 4 * grp + (j >> 1), kc = j & 1;
         if (s < 2 && tap < 27 && mrow < m_n) val = W[(mrow * CIN[l] + kc) * 27 + tap];
       } else {
-        const int tap = 2 * s + (grp >> 1);
+        const int half = grp >> 1;
+        const int tap = tap16(s, half);
         const int kc = (grp & 1) * 8 + j;
-        if (tap < 27 && mrow < m_n && kc < ci_n) {
+        if (!pad16(s, half) && mrow < m_n && kc < ci_n) {
           if (!flip) val = W[(mrow * CIN[l] + kc) * 27 + tap];
           else val = W[(kc * CIN[l] + mrow) * 27 + (26 - tap)];
         }
@@ -705,10 +835,11 @@ static int check_grid(const tbs_net* n, const int64_t grid[3]) {
   return TBS_OK;
 }
 
-// persistent grid: enough workgroups to fill the 256 CUs several times, each looping over tiles
+// one workgroup per (32 x 8 column, z-chunk)
 static int conv_blocks(const int64_t grid[3]) {
-  const int64_t tiles = ((grid[0] + CTX - 1) / CTX) * ((grid[1] + CTY - 1) / CTY) * ((grid[2] + CTZ - 1) / CTZ);
-  return (int)std::min<int64_t>(tiles, 2048);
+  const Grid3 g{(int)grid[0], (int)grid[1], (int)grid[2], 0};
+  const ConvGeo c = conv_geo(g);
+  return c.tx * c.ty * c.nch;
 }
 
 static int smooth(tbs_net* n, float* buf, float* tmp, Grid3 g);
