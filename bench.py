@@ -228,8 +228,24 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N):
         gd[name] = {"GDoF/s": round(N / (ms / cnt / 1e3) / 1e9, 1), "GB/s": round(by / (ms / 1e3) / 1e9, 1),
                     "frac_hbm": round(by / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "ms": round(ms / cnt, 4)}
         log("apply %s: %s" % (name, gd[name]))
+    # practical ceiling: a plain device-to-device copy of the FP32 field (read 4 B + write 4 B per DoF)
+    with torch.cuda.stream(stream):
+        for _ in range(2):
+            y32.copy_(u32)
+        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        c0.record(stream)
+        for _ in range(10):
+            y32.copy_(u32)
+        c1.record(stream)
+    torch.cuda.synchronize()
+    copy_gbs = 8 * N / (c0.elapsed_time(c1) / 10 / 1e3) / 1e9
+    res["copy_ceiling"] = {"GB/s": round(copy_gbs, 1), "frac_hbm": round(copy_gbs / HBM_PEAK_GBS, 4),
+                           "kernel": "torch copy_ of the FP32 928^3 field"}
+    for v in gd.values():
+        v["frac_copy"] = round(v["GB/s"] / copy_gbs, 4)
     res["apply"] = gd
     del y64, u32, y32, u16
+    res["apply_degree_sweep"] = degree_sweep(tbs, torch)
 
     def time_steps(prec, use_net, k):
         ua, ub = u0.clone(), torch.empty_like(u0)
@@ -268,6 +284,38 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N):
         log("net forward: %.4f s" % res["net_forward_s"])
         del du
     return res
+
+
+def degree_sweep(tbs, torch):
+    """FP32 apply on the anisotropic periodic 1024 x 512 x 256 grid for quadratic, cubic and
+    quintic splines (5, 7, 11 taps per 1-D pass), seeded N(0,1) field."""
+    import workloads
+    w = workloads.HEAT_1024x512x256_PERIODIC
+    N = w.grid[0] * w.grid[1] * w.grid[2]
+    g = torch.Generator(device="cuda")
+    g.manual_seed(4)
+    u = torch.randn(w.grid[::-1], generator=g, device="cuda", dtype=torch.float32)
+    y = torch.empty_like(u)
+    out = {}
+    for n in (2, 3, 5):
+        ctx = tbs.Context(w.grid, n, w.h, w.tau, w.bc)
+        ctx.ensure_workspace(-1)
+        for _ in range(2):
+            ctx.apply(u, y)
+        torch.cuda.synchronize()
+        ctx.prof_enable(True)
+        for _ in range(20):
+            ctx.apply(u, y)
+        ms, by, cnt = list(ctx.prof_read().values())[0]
+        ctx.prof_enable(False)
+        gbs = by / (ms / 1e3) / 1e9
+        out["n%d" % n] = {"taps": 2 * n + 1, "GDoF/s": round(N / (ms / cnt / 1e3) / 1e9, 1), "GB/s": round(gbs, 1),
+                          "frac_hbm": round(gbs / HBM_PEAK_GBS, 4), "ms": round(ms / cnt, 4)}
+        log("degree sweep n=%d: %s" % (n, out["n%d" % n]))
+        del ctx
+    out["grid"] = list(w.grid)
+    out["bc"] = w.bc
+    return out
 
 
 def cpu_baseline(w, params, sp):

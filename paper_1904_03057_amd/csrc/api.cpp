@@ -112,10 +112,11 @@ static bool aligned_ptr(const void* p) { return p && ((uintptr_t)p & 255u) == 0;
 
 static void plan_geometry(tbs_ctx* c, int zchunk) {
   c->tiles_x = (int)((c->nx + kTileX - 1) / kTileX);
-  c->tiles_y = (int)((c->ny + kTileY - 1) / kTileY);
+  c->tiles_y = (int)((c->ny + kTileY - 1) / kTileY);  // finest tiling: bounds the partial-sum count
   const int64_t tiles = (int64_t)c->tiles_x * c->tiles_y;
+  const int64_t plan_tiles = (int64_t)c->tiles_x * ((c->ny + kTileYPlan - 1) / kTileYPlan);
   // enough blocks to fill 256 CUs several times, but chunks of at least 4(2n+1) planes
-  int64_t want = (4096 + tiles - 1) / tiles;
+  int64_t want = (4096 + plan_tiles - 1) / plan_tiles;
   const int64_t minzc = std::max<int64_t>(16, 4 * (2 * c->n + 1));
   int64_t maxchunks = std::max<int64_t>(1, c->nz / minzc);
   int64_t chunks = std::min(want, maxchunks);

@@ -12,16 +12,21 @@
 #ifndef STENCIL_CG_TY
 #define STENCIL_CG_TY 16
 #endif
+#ifndef STENCIL_RESID_TY
+#define STENCIL_RESID_TY 8
+#endif
 
 namespace tbs {
 
 constexpr int kTileX = 64;
-constexpr int kTileY = STENCIL_TY;  // smallest tile height: sizes the partial-sum buffers
+constexpr int kTileY = STENCIL_RESID_TY < STENCIL_TY ? STENCIL_RESID_TY : STENCIL_TY;  // smallest tile height: sizes the partial-sum buffers
+constexpr int kTileYPlan = 16;  // tile height the z-chunk plan assumes
 
 // Tile height per (mode, compute precision): taller tiles re-read fewer halo rows; the FP64
-// kernels keep 16 rows for register room.
+// kernels keep 16 rows for register room, and the FP64 residual (two FP64 inputs) 8.
 constexpr int stencil_tile_y(int mode, int compute_bytes) {
-  return compute_bytes == 4 ? ((mode == M_APPLY) ? 32 : (mode == M_CG1 ? STENCIL_CG_TY : 16)) : 16;
+  return compute_bytes == 4 ? ((mode == M_APPLY) ? 32 : (mode == M_CG1 ? STENCIL_CG_TY : 16))
+                            : (mode == M_RESID ? STENCIL_RESID_TY : 16);
 }
 // Number of workgroups (= partial sums written) of a stencil launch of this mode.
 int stencil_blocks(const StencilArgs& a, int mode, int compute_bytes);

@@ -154,10 +154,11 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
 
   // prefetch registers: primary input vector (u / u_prev / p_old / x), secondary (q / r), x (CG1)
   // two prefetch slots: plane k is staged from slot (k - kbeg) & 1 while plane k+1 is in flight
-  Raw pa[2][NV];
-  RawC pb[2][NV];
-  RawC px[2][NVC];
-  int pk[2] = {0, 0};  // plane index held in each prefetch slot
+  constexpr int PF = MODE == M_RESID ? 1 : 2;  // prefetch distance (planes); 1 keeps the residual's registers low
+  Raw pa[PF][NV];
+  RawC pb[PF][NV];
+  RawC px[PF][NVC];
+  int pk[PF] = {};  // plane index held in each prefetch slot
 
   auto fetch = [&](int k, const int sl) {
     bool pvalid = true;
@@ -246,7 +247,7 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
 
   const int kbeg = z0 - N, kend = z0 + zc_eff + N;
   fetch(kbeg, 0);
-  if (kbeg + 1 < kend) fetch(kbeg + 1, 1);
+  if (PF == 2 && kbeg + 1 < kend) fetch(kbeg + 1, PF - 1);
   // unrolled over 2T planes: ring slot (ph + d) mod T and prefetch slot ph & 1 are static
   for (int kb = kbeg; kb < kend; kb += 2 * T) {
 #pragma clang loop unroll(full)
@@ -254,9 +255,9 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
       const int k = kb + ph;
       if (k < kend) {  // uniform: keeps the trip count constant so the ring indices are static
       const bool active = (BC == BC_PERIODIC) || (k >= 0 && k < nz);
-      if (active) stage_plane(ph & 1);
+      if (active) stage_plane(ph % PF);
       __syncthreads();
-      if (k + 2 < kend) fetch(k + 2, ph & 1);
+      if (k + PF < kend) fetch(k + PF, ph % PF);
       if (active) {
         if constexpr (MODE == M_CG1) {
           const int qs = ((k % QD) + QD) % QD;
