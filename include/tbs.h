@@ -81,6 +81,13 @@ typedef struct {
                               do not depend on it (each output sums its terms in the same order) */
   int tile_order;          /* stencil tile order: 0 x-tiles fastest, 1 y-tiles fastest (no effect on results) */
   int nt_store;            /* 1: stencil outputs use non-temporal stores (no effect on results) */
+  int fused_cg;            /* FP32 inner CG (TBS_PREC_FP32, MIXED, MIXED_BF16, tbs_cg_step in F32):
+                              1 = one kernel per iteration (default): r and p formed while staging,
+                              q = A p, and FP64 sums of p.q, r.q, q.q and r.r; alpha = r.r / p.q from
+                              the explicit r.r, beta and the stopping test from the one-step
+                              prediction r.r - 2 alpha r.q + alpha^2 q.q; 0 = the two-kernel
+                              Hestenes-Stiefel iteration (q = A p and p.q, then r -= alpha q and r.r).
+                              The FP64 CG always uses the two-kernel form. */
 } tbs_opts;
 
 /* ---------------------------------------------------------------- context ---------------- */
@@ -206,8 +213,9 @@ int tbs_net_get_grad(const tbs_net* net, float* host, size_t n);
  * algorithmic bytes (the bytes the method must move: each input element read once, each output
  * written once).  CG launches that found the solve already converged are not counted.
  * Kinds: 0 apply f64, 1 apply f32, 2 apply bf16->f32, 3 rhs f64, 4 rhs f32, 5 cg-fused f64,
- * 6 cg-fused f32, 7 cg-fused f32 with bf16 p, 8 residual f64, 9 cg-update f64, 10 cg-update f32. */
-#define TBS_PROF_KINDS 11
+ * 6 cg-fused f32, 7 cg-fused f32 with bf16 p, 8 residual f64, 9 cg-update f64, 10 cg-update f32,
+ * 11 one-kernel CG iteration f32, 12 one-kernel CG iteration f32 with bf16 p. */
+#define TBS_PROF_KINDS 13
 int tbs_prof_enable(tbs_ctx* ctx, int on);   /* resets the counters */
 int tbs_prof_read(tbs_ctx* ctx, int kind, double* total_ms, double* total_bytes, int64_t* launches);
 

@@ -37,7 +37,8 @@ EXPORTS = [
     "tbs_last_error",
 ]
 PROF_KINDS = ["apply_f64", "apply_f32", "apply_bf16_f32", "rhs_f64", "rhs_f32", "cg_fused_f64", "cg_fused_f32",
-              "cg_fused_f32_bf16p", "residual_f64", "cg_update_f64", "cg_update_f32"]
+              "cg_fused_f32_bf16p", "residual_f64", "cg_update_f64", "cg_update_f32", "cg_iter_f32",
+              "cg_iter_f32_bf16p"]
 
 
 class Stats(ctypes.Structure):
@@ -52,7 +53,7 @@ class Stats(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("inner_rtol", ctypes.c_double), ("inner_max_iter", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("poll_every", ctypes.c_int), ("zchunk", ctypes.c_int),
-                ("tile_order", ctypes.c_int), ("nt_store", ctypes.c_int)]
+                ("tile_order", ctypes.c_int), ("nt_store", ctypes.c_int), ("fused_cg", ctypes.c_int)]
 
 
 _vp, _i64p, _dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
@@ -182,8 +183,8 @@ class Context:
         return list(m), list(s)
 
     def set_opts(self, inner_rtol=1e-4, inner_max_iter=500, max_sweeps=12, poll_every=4, zchunk=0,
-                 tile_order=0, nt_store=0):
-        o = Opts(inner_rtol, inner_max_iter, max_sweeps, poll_every, zchunk, tile_order, nt_store)
+                 tile_order=0, nt_store=0, fused_cg=1):
+        o = Opts(inner_rtol, inner_max_iter, max_sweeps, poll_every, zchunk, tile_order, nt_store, fused_cg)
         _check(_lib.tbs_set_opts(self._h, ctypes.byref(o)), "tbs_set_opts")
         if self._ws is not None and self._ws.numel() < self.workspace_bytes(-1):
             self._ws = None

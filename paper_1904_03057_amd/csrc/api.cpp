@@ -128,9 +128,9 @@ static void plan_geometry(tbs_ctx* c, int zchunk) {
   c->nparts = std::max(c->nblocks, kVecBlocks);
 }
 
-// workspace layout: [scalars x4][part0][part1][arrays...]
+// workspace layout: [scalars x4][part0][part1][part2][part3][arrays...]
 enum { SC_CG = 0, SC_AUX = 1 };
-static size_t ws_head(const tbs_ctx* c) { return 1024 + 2 * align256((size_t)c->nparts * 8); }
+static size_t ws_head(const tbs_ctx* c) { return 1024 + 4 * align256((size_t)c->nparts * 8); }
 
 struct Layout {
   size_t bytes;
@@ -146,12 +146,12 @@ static Layout layout(const tbs_ctx* c, int prec) {
     case -1: break;
     case TBS_PREC_FP64:  // b, r, pA, pB, q
       put(0, 8); put(1, 8); put(2, 8); put(3, 8); put(4, 8); break;
-    case TBS_PREC_FP32:  // b, x, r, pA, pB, q (f32)
-      put(0, 4); put(1, 4); put(2, 4); put(3, 4); put(4, 4); put(5, 4); break;
-    case TBS_PREC_MIXED:  // b64, r32, d, pA, pB, q
-      put(0, 8); put(1, 4); put(2, 4); put(3, 4); put(4, 4); put(5, 4); break;
-    case TBS_PREC_MIXED_BF16:  // b64, r32, d, pA(bf16), pB(bf16), q
-      put(0, 8); put(1, 4); put(2, 4); put(3, 2); put(4, 2); put(5, 4); break;
+    case TBS_PREC_FP32:  // b, x, r, pA, pB, q, rB, qB (f32; rB, qB: second r, q of the one-kernel iteration)
+      put(0, 4); put(1, 4); put(2, 4); put(3, 4); put(4, 4); put(5, 4); put(6, 4); put(7, 4); break;
+    case TBS_PREC_MIXED:  // b64, r32, d, pA, pB, q, rB, qB
+      put(0, 8); put(1, 4); put(2, 4); put(3, 4); put(4, 4); put(5, 4); put(6, 4); put(7, 4); break;
+    case TBS_PREC_MIXED_BF16:  // b64, r32, d, pA(bf16), pB(bf16), q, rB, qB
+      put(0, 8); put(1, 4); put(2, 4); put(3, 2); put(4, 2); put(5, 4); put(6, 4); put(7, 4); break;
   }
   L.bytes = o;
   return L;
@@ -160,6 +160,8 @@ static Layout layout(const tbs_ctx* c, int prec) {
 static Scalars* scal(const tbs_ctx* c, int slot) { return (Scalars*)(c->ws + slot * 256); }
 static double* part0(const tbs_ctx* c) { return (double*)(c->ws + 1024); }
 static double* part1(const tbs_ctx* c) { return (double*)(c->ws + 1024 + align256((size_t)c->nparts * 8)); }
+static double* part2(const tbs_ctx* c) { return (double*)(c->ws + 1024 + 2 * align256((size_t)c->nparts * 8)); }
+static double* part3(const tbs_ctx* c) { return (double*)(c->ws + 1024 + 3 * align256((size_t)c->nparts * 8)); }
 
 static StencilArgs base_args(const tbs_ctx* c) {
   StencilArgs a{};
@@ -168,6 +170,8 @@ static StencilArgs base_args(const tbs_ctx* c) {
   a.t = c->taps;
   a.part0 = part0(c);
   a.part1 = part1(c);
+  a.part2 = part2(c);
+  a.part3 = part3(c);
   a.order = c->opts.tile_order;
   a.nt_store = c->opts.nt_store;
   return a;
@@ -209,6 +213,7 @@ extern "C" int tbs_setup(tbs_ctx** out, const int64_t grid[3], int degree, const
   c->opts.zchunk = 0;
   c->opts.tile_order = 0;
   c->opts.nt_store = 0;
+  c->opts.fused_cg = 1;
   *out = c;
   return TBS_OK;
 }
@@ -315,11 +320,11 @@ extern "C" int tbs_set_opts(tbs_ctx* c, const tbs_opts* o) {
   if (!c) return set_err(TBS_E_INVAL, "null context");
   if (!o) {
     c->opts.inner_rtol = 1e-4; c->opts.inner_max_iter = 500; c->opts.max_sweeps = 12; c->opts.poll_every = 4;
-    c->opts.zchunk = 0; c->opts.tile_order = 0; c->opts.nt_store = 0;
+    c->opts.zchunk = 0; c->opts.tile_order = 0; c->opts.nt_store = 0; c->opts.fused_cg = 1;
   } else {
     if (!(o->inner_rtol > 0 && o->inner_rtol < 1) || o->inner_max_iter < 1 || o->max_sweeps < 1 ||
         o->poll_every < 1 || o->zchunk < 0 || o->tile_order < 0 || o->tile_order > 1 || o->nt_store < 0 ||
-        o->nt_store > 1)
+        o->nt_store > 1 || o->fused_cg < 0 || o->fused_cg > 1)
       return set_err(TBS_E_INVAL, "bad options");
     c->opts = *o;
   }
@@ -455,6 +460,8 @@ struct CgArrays {
   void* r;
   void* p[2];
   void* q;
+  void* r2;  // one-kernel iteration: r and q alternate between (r, r2) and (q, q2)
+  void* q2;
 };
 
 static int cg1_async(tbs_ctx* c, const CgArrays& A, int dt, int k) {
@@ -481,6 +488,34 @@ static int cg1_async(tbs_ctx* c, const CgArrays& A, int dt, int k) {
   return TBS_OK;
 }
 
+// One-kernel CG iteration k (FP32 vectors): r_k = r_{k-1} - alpha q_{k-1}, p_k = r_k + beta p_{k-1},
+// x += alpha p_{k-1}, q_k = A p_k and the FP64 partial sums of p.q, r.q, q.q and r.r in one stencil
+// launch, then one reduction.  r, p and q alternate between two arrays (halo reads of the old
+// values and writes of the new ones overlap in one launch).
+static int cgf_async(tbs_ctx* c, const CgArrays& A, int dt, int k) {
+  StencilArgs a = base_args(c);
+  void* R[2] = {A.r, A.r2};
+  void* Q[2] = {A.q, A.q2};
+  a.in0 = R[k & 1];
+  a.in1 = A.p[k & 1];
+  a.in2 = Q[k & 1];
+  a.out0 = Q[(k + 1) & 1];
+  a.out1 = A.p[(k + 1) & 1];
+  a.out2 = R[(k + 1) & 1];
+  a.io0 = A.x;
+  a.scal = scal(c, SC_CG);
+  a.first = (k == 0);
+  const double tp = dt == 1 ? 4 : 2;
+  // first iteration: read r, write r, p, q; later: read r, q, p_old, x, write r, p, q, x
+  const double b1 = (double)c->N * (k == 0 ? (12 + tp) : (2 * (12 + tp)));
+  int ps = prof_begin(c, dt == 1 ? 11 : 12, k, b1);
+  HIPCHK(launch_cgf(a, c->n, c->bc, dt, c->st));
+  prof_end(c, ps);
+  HIPCHK(launch_finalize(FIN_FUSED, part0(c), part1(c), stencil_blocks(a, M_CGF, 4), scal(c, SC_CG), 0.0, c->st,
+                         part2(c), part3(c)));
+  return TBS_OK;
+}
+
 // Runs CG iterations k = k0 .. until done / max_iter, then flushes the pending x update.
 // Returns TBS_OK, TBS_W_NOT_CONVERGED or TBS_E_BREAKDOWN; *nit receives the completed count.
 static int cg_loop(tbs_ctx* c, const CgArrays& A, int dt, int k0, int max_iter, int* nit) {
@@ -491,7 +526,7 @@ static int cg_loop(tbs_ctx* c, const CgArrays& A, int dt, int k0, int max_iter, 
   while (!s.done && k < max_iter) {
     const int batch = std::min(c->opts.poll_every, max_iter - k);
     for (int i = 0; i < batch; ++i) {
-      rc = cg1_async(c, A, dt, k++);
+      rc = (dt != 0 && c->opts.fused_cg) ? cgf_async(c, A, dt, k++) : cg1_async(c, A, dt, k++);
       if (rc) return rc;
     }
     rc = read_scal(c, SC_CG, &s);
@@ -531,8 +566,12 @@ extern "C" int tbs_cg_begin(tbs_ctx* c, const void* b, void* x, int dt, double r
   const Layout L = layout(c, prec);
   CgArrays A;
   A.x = x;
+  A.r2 = A.q2 = nullptr;
   if (dt == TBS_F64) { A.r = c->ws + L.off[1]; A.p[0] = c->ws + L.off[2]; A.p[1] = c->ws + L.off[3]; A.q = c->ws + L.off[4]; }
-  else { A.r = c->ws + L.off[2]; A.p[0] = c->ws + L.off[3]; A.p[1] = c->ws + L.off[4]; A.q = c->ws + L.off[5]; }
+  else {
+    A.r = c->ws + L.off[2]; A.p[0] = c->ws + L.off[3]; A.p[1] = c->ws + L.off[4]; A.q = c->ws + L.off[5];
+    A.r2 = c->ws + L.off[6]; A.q2 = c->ws + L.off[7];
+  }
   rc = cg_init_async(c, b, A, dt == TBS_F64 ? 0 : 1, rtol);
   if (rc) return rc;
   c->cg_active = 1;
@@ -552,8 +591,12 @@ extern "C" int tbs_cg_step(tbs_ctx* c, int n_iters, double* rel_res_out, int* it
   const Layout L = layout(c, prec);
   CgArrays A;
   A.x = c->cg_x;
+  A.r2 = A.q2 = nullptr;
   if (c->cg_dt == TBS_F64) { A.r = c->ws + L.off[1]; A.p[0] = c->ws + L.off[2]; A.p[1] = c->ws + L.off[3]; A.q = c->ws + L.off[4]; }
-  else { A.r = c->ws + L.off[2]; A.p[0] = c->ws + L.off[3]; A.p[1] = c->ws + L.off[4]; A.q = c->ws + L.off[5]; }
+  else {
+    A.r = c->ws + L.off[2]; A.p[0] = c->ws + L.off[3]; A.p[1] = c->ws + L.off[4]; A.q = c->ws + L.off[5];
+    A.r2 = c->ws + L.off[6]; A.q2 = c->ws + L.off[7];
+  }
   int nit = 0;
   rc = cg_loop(c, A, c->cg_dt == TBS_F64 ? 0 : 1, c->cg_enq, c->cg_enq + n_iters, &nit);
   c->cg_enq = nit;
@@ -648,7 +691,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
 
   int result = TBS_OK;
   if (prec == TBS_PREC_FP64) {
-    CgArrays A{u_next, c->ws + L.off[1], {c->ws + L.off[2], c->ws + L.off[3]}, c->ws + L.off[4]};
+    CgArrays A{u_next, c->ws + L.off[1], {c->ws + L.off[2], c->ws + L.off[3]}, c->ws + L.off[4], nullptr, nullptr};
     rc = cg_init_async(c, b64, A, 0, rtol);
     if (rc) return rc;
     Scalars s;
@@ -671,7 +714,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     if (q) HIPCHK(launch_convert(q, 0, r32, 1, c->N, c->st));
     rc = tbs_rhs(c, x32, q ? r32 : nullptr, b32, TBS_F32);
     if (rc) return rc;
-    CgArrays A{x32, r32, {c->ws + L.off[3], c->ws + L.off[4]}, c->ws + L.off[5]};
+    CgArrays A{x32, r32, {c->ws + L.off[3], c->ws + L.off[4]}, c->ws + L.off[5], c->ws + L.off[6], c->ws + L.off[7]};
     rc = cg_init_async(c, b32, A, 1, rtol);
     if (rc) return rc;
     Scalars s;
@@ -696,7 +739,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     const int dt = (prec == TBS_PREC_MIXED_BF16) ? 2 : 1;
     float* r32 = (float*)(c->ws + L.off[1]);
     float* d32 = (float*)(c->ws + L.off[2]);
-    CgArrays A{d32, r32, {c->ws + L.off[3], c->ws + L.off[4]}, c->ws + L.off[5]};
+    CgArrays A{d32, r32, {c->ws + L.off[3], c->ws + L.off[4]}, c->ws + L.off[5], c->ws + L.off[6], c->ws + L.off[7]};
     int total = 0, sweeps = 0;
     for (;;) {
       Scalars s;

@@ -29,7 +29,9 @@ struct Scalars {
   int pending;    // 1: x += alpha * p of iteration nit-1 still to be applied
 };
 
-enum Mode { M_APPLY = 0, M_RHS = 1, M_CG1 = 2, M_RESID = 3 };
+// CG1: one half of a Hestenes-Stiefel iteration (p, x update, q = A p, p.q); CGF: a whole iteration
+// in one kernel (r update, p, x update, q = A p and the dot products p.q, r.q, q.q, r.r).
+enum Mode { M_APPLY = 0, M_RHS = 1, M_CG1 = 2, M_RESID = 3, M_CGF = 4 };
 enum Bc { BC_PERIODIC = 0, BC_DIRICHLET = 1 };
 
 struct StencilArgs {
@@ -37,15 +39,19 @@ struct StencilArgs {
   int tiles_x, tiles_y, nchunks, nblocks;
   Taps t;
   const void* in0;             // APPLY: u  RHS: u_prev  CG1: r  RESID: x
-  const void* in1;             // RHS: q (nullable)  CG1: p_old
-  void* out0;                  // APPLY: y  RHS: b  CG1: q  RESID: r (nullable)
-  void* out1;                  // CG1: p_new
-  void* io0;                   // CG1: x (lazy update, nullable)
+  const void* in1;             // RHS: q (nullable)  CG1, CGF: p_old
+  const void* in2;             // CGF: q_old
+  void* out0;                  // APPLY: y  RHS: b  CG1, CGF: q  RESID: r (nullable)
+  void* out1;                  // CG1, CGF: p_new
+  void* out2;                  // CGF: r_new
+  void* io0;                   // CG1, CGF: x (lazy update, nullable)
   const double* bvec;          // RESID: b
-  double* part0;               // per-block partial sums (CG1: p.q, RESID: r.r)
-  double* part1;               // RESID: b.b
-  const Scalars* scal;         // CG1: alpha, beta, done, pending
-  int first;                   // CG1: first iteration (p = r)
+  double* part0;               // per-block partial sums (CG1, CGF: p.q, RESID: r.r)
+  double* part1;               // RESID: b.b  CGF: r.q
+  double* part2;               // CGF: q.q
+  double* part3;               // CGF: r.r (of r_new)
+  const Scalars* scal;         // CG1, CGF: alpha, beta, done, pending
+  int first;                   // CG1, CGF: first iteration (p = r)
   int order;                   // tile order: 0 x-tiles fastest, 1 y-tiles fastest
   int nt_store;                // 1: outputs written with non-temporal stores
 };

@@ -12,6 +12,12 @@
 #ifndef STENCIL_CG_TY
 #define STENCIL_CG_TY 16
 #endif
+#ifndef STENCIL_CGF_TY
+#define STENCIL_CGF_TY 16
+#endif
+#ifndef STENCIL_CG_PF
+#define STENCIL_CG_PF 1
+#endif
 #ifndef STENCIL_RESID_TY
 #define STENCIL_RESID_TY 8
 #endif
@@ -19,13 +25,14 @@
 namespace tbs {
 
 constexpr int kTileX = 64;
-constexpr int kTileY = STENCIL_RESID_TY < STENCIL_TY ? STENCIL_RESID_TY : STENCIL_TY;  // smallest tile height: sizes the partial-sum buffers
+constexpr int kTileYMin2 = STENCIL_RESID_TY < STENCIL_CGF_TY ? STENCIL_RESID_TY : STENCIL_CGF_TY;
+constexpr int kTileY = kTileYMin2 < STENCIL_TY ? kTileYMin2 : STENCIL_TY;  // smallest tile height: sizes the partial-sum buffers
 constexpr int kTileYPlan = 16;  // tile height the z-chunk plan assumes
 
 // Tile height per (mode, compute precision): taller tiles re-read fewer halo rows; the FP64
 // kernels keep 16 rows for register room, and the FP64 residual (two FP64 inputs) 8.
 constexpr int stencil_tile_y(int mode, int compute_bytes) {
-  return compute_bytes == 4 ? ((mode == M_APPLY) ? 32 : (mode == M_CG1 ? STENCIL_CG_TY : 16))
+  return compute_bytes == 4 ? ((mode == M_APPLY) ? 32 : (mode == M_CG1 ? STENCIL_CG_TY : (mode == M_CGF ? STENCIL_CGF_TY : 16)))
                             : (mode == M_RESID ? STENCIL_RESID_TY : 16);
 }
 // Number of workgroups (= partial sums written) of a stencil launch of this mode.
@@ -35,6 +42,8 @@ int stencil_blocks(const StencilArgs& a, int mode, int compute_bytes);
 hipError_t launch_apply(const StencilArgs& a, int n, int bc, int in_dt, int out_dt, hipStream_t st);
 hipError_t launch_rhs(const StencilArgs& a, int n, int bc, int dt, hipStream_t st);
 hipError_t launch_cg1(const StencilArgs& a, int n, int bc, int dt, hipStream_t st);
+// CGF (one-kernel CG iteration): dt = 1 (all f32), 2 (f32 with p stored as bf16)
+hipError_t launch_cgf(const StencilArgs& a, int n, int bc, int dt, hipStream_t st);
 hipError_t launch_resid(const StencilArgs& a, int n, int bc, int r_dt, hipStream_t st);
 
 // vector.hip
@@ -50,8 +59,11 @@ hipError_t launch_fill(void* x, int dt, int64_t n, hipStream_t st);  // zero fil
 hipError_t launch_guess_combine(double* x, const double* u, const float* du, int64_t n, hipStream_t st);
 
 // finalize kernels (single block, fixed-order reduction of partial sums)
-enum FinOp { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_DOT = 3, FIN_NORMS = 4, FIN_CLEAR_PENDING = 5 };
+enum FinOp { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_DOT = 3, FIN_NORMS = 4, FIN_CLEAR_PENDING = 5,
+             FIN_FUSED = 6 };
+// Reduces the per-block partial sums p0 (and p1, p2, p3 where the op uses them) in a fixed order
+// and updates the CG scalars.  FIN_FUSED takes p.q, r.q, q.q and r.r of a CGF launch.
 hipError_t launch_finalize(int op, const double* p0, const double* p1, int count, Scalars* s, double rtol,
-                           hipStream_t st);
+                           hipStream_t st, const double* p2 = nullptr, const double* p3 = nullptr);
 
 }  // namespace tbs

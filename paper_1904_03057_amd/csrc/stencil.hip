@@ -52,16 +52,23 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
   constexpr int NVH = (HALO + NT - 1) / NT;        // halo vectors per thread
   constexpr int NV = NVC + NVH;
   constexpr int RPW = TY / 4;                      // output rows per wave
-  constexpr int QD = (MODE == M_CG1) ? N + 1 : 1;  // depth of the centre-value ring (CG1)
+  constexpr bool CG = (MODE == M_CG1 || MODE == M_CGF);
+  constexpr bool FUSED = (MODE == M_CGF);
+  constexpr int QD = CG ? N + 1 : 1;  // depth of the centre-value rings (CG1, CGF)
   static_assert(TY % 4 == 0, "TY must be a multiple of 4");
 
   __shared__ Tc stage[R * C];
   __shared__ Tc su[R * TX];
   __shared__ Tc sv[R * TX];
-  __shared__ Tc cring[QD * TY * TX];  // p at the own points of the last n+1 planes (CG1 dot product)
-  __shared__ double red[2][4 * WX];
+  __shared__ Tc cring[QD * TY * TX];  // p at the own points of the last n+1 planes (p.q)
+  // CGF: r at the own points of the last n+2 planes (r.q).  It is written while a plane is staged,
+  // before the barrier that follows, so it keeps one plane more than cring: the slot being written
+  // is never the one the previous plane's outputs are still reading.
+  constexpr int RQD = FUSED ? N + 2 : 1;
+  __shared__ Tc rring[FUSED ? RQD * TY * TX : 1];
+  __shared__ double red[4][4 * WX];
 
-  if (MODE == M_CG1 && a.scal->done) return;
+  if (CG && a.scal->done) return;
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -102,6 +109,7 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
   // plane-invariant placement of this thread's staged vectors: core (own-point) vectors in
   // slots 0..NVC-1, halo vectors (top/bottom rows, then left/right columns) after them
   int off[NV], soff[NV];
+  int coff[NVC];  // CGF: tile-relative position (row * TX + column) of each core vector
   uint32_t valid = 0, own = 0;
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
@@ -112,6 +120,7 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
       present = idx < CORE;
       r = N + idx / (TX / VE);
       cv = HX / VE + idx % (TX / VE);
+      coff[v < NVC ? v : 0] = (r - N) * TX + (cv - HX / VE) * VE;
     } else {
       int idx = tid + NT * (v - NVC);
       present = idx < HALO;
@@ -147,18 +156,21 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
     }
   }
 
-  const Tc beta = (MODE == M_CG1 && !a.first) ? (Tc)a.scal->beta : (Tc)0;
-  const Tc alpha_prev = (MODE == M_CG1) ? (Tc)a.scal->alpha : (Tc)0;
-  const bool xupd = (MODE == M_CG1) && a.io0 != nullptr && !a.first && a.scal->pending;
+  const Tc beta = (CG && !a.first) ? (Tc)a.scal->beta : (Tc)0;
+  const Tc alpha_prev = CG ? (Tc)a.scal->alpha : (Tc)0;
+  const bool xupd = CG && a.io0 != nullptr && !a.first && a.scal->pending;
   const Tc tauc = (Tc)a.t.tau;
 
   // prefetch registers: primary input vector (u / u_prev / p_old / x), secondary (q / r), x (CG1)
   // two prefetch slots: plane k is staged from slot (k - kbeg) & 1 while plane k+1 is in flight
-  constexpr int PF = MODE == M_RESID ? 1 : 2;  // prefetch distance (planes); 1 keeps the residual's registers low
+  // prefetch distance (planes); 1 keeps the registers of the residual (and CG1) low
+  constexpr int PF = MODE == M_RESID ? 1 : (CG ? STENCIL_CG_PF : 2);
   Raw pa[PF][NV];
   RawC pb[PF][NV];
   RawC px[PF][NVC];
+  RawC pq[FUSED ? PF : 1][FUSED ? NV : 1];  // CGF: q_old
   int pk[PF] = {};  // plane index held in each prefetch slot
+  double part0 = 0.0, part1 = 0.0, part2 = 0.0, part3 = 0.0;
 
   auto fetch = [&](int k, const int sl) {
     bool pvalid = true;
@@ -178,6 +190,7 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
         pa[sl][v].x[e] = (Tin)0;
         pb[sl][v].x[e] = (Tc)0;
         if (v < NVC) px[sl][v < NVC ? v : 0].x[e] = (Tc)0;
+        if (FUSED) pq[FUSED ? sl : 0][FUSED ? v : 0].x[e] = (Tc)0;
       }
       if (pvalid && ((valid >> v) & 1u)) {
         const int64_t gi = base + off[v];
@@ -186,9 +199,10 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
         } else if (MODE == M_RHS) {
           pa[sl][v] = *(const Raw*)((const Tin*)a.in0 + gi);
           if (a.in1) pb[sl][v] = *(const RawC*)((const Tc*)a.in1 + gi);
-        } else {  // CG1: in0 = r (Tc), in1 = p_old (Tin), io0 = x (Tc)
+        } else {  // CG1, CGF: in0 = r (Tc), in1 = p_old (Tin), in2 = q_old (Tc, CGF), io0 = x (Tc)
           pb[sl][v] = *(const RawC*)((const Tc*)a.in0 + gi);
           if (!a.first) pa[sl][v] = *(const Raw*)((const Tin*)a.in1 + gi);
+          if (FUSED && !a.first) pq[FUSED ? sl : 0][FUSED ? v : 0] = *(const RawC*)((const Tc*)a.in2 + gi);
           if (v < NVC && xupd && inchunk && ((own >> v) & 1u))
             px[sl][v < NVC ? v : 0] = *(const RawC*)((const Tc*)a.io0 + gi);
         }
@@ -215,20 +229,34 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
           for (int e = 0; e < VE; ++e) dst[e] = fmad(tauc, pb[sl][v].x[e], to_c<Tin, Tc>(pa[sl][v].x[e]));
         } else {
           Raw pn;
-          RawC xn;
+          RawC xn, rn;
           const bool ow = v < NVC && inchunk && ((own >> v) & 1u) && ((valid >> v) & 1u);
 #pragma unroll
           for (int e = 0; e < VE; ++e) {
             const Tc pold = to_c<Tin, Tc>(pa[sl][v].x[e]);
-            const Tc val = storage_round<Tin, Tc>(fmad(beta, pold, pb[sl][v].x[e]));
+            Tc rv = pb[sl][v].x[e];
+            // CGF: r_k = r_{k-1} - alpha_{k-1} q_{k-1} at every staged point (halo included)
+            if (FUSED && !a.first) rv = fmad(-alpha_prev, pq[FUSED ? sl : 0][FUSED ? v : 0].x[e], rv);
+            const Tc val = storage_round<Tin, Tc>(fmad(beta, pold, rv));
             dst[e] = val;
             pn.x[e] = from_c<Tin, Tc>(val);
+            rn.x[e] = rv;
             if (v < NVC) xn.x[e] = fmad(alpha_prev, pold, px[sl][v < NVC ? v : 0].x[e]);
+          }
+          if (FUSED && v < NVC) {
+            const int rs = ((k % RQD) + RQD) % RQD;
+#pragma unroll
+            for (int e = 0; e < VE; ++e) rring[rs * TY * TX + coff[v < NVC ? v : 0] + e] = rn.x[e];
           }
           if (ow) {
             const int64_t gi = base + off[v];
             *(Raw*)((Tin*)a.out1 + gi) = pn;
             if (xupd) *(RawC*)((Tc*)a.io0 + gi) = xn;
+            if (FUSED) {
+              *(RawC*)((Tc*)a.out2 + gi) = rn;
+#pragma unroll
+              for (int e = 0; e < VE; ++e) part3 = fma((double)rn.x[e], (double)rn.x[e], part3);
+            }
           }
         }
       }
@@ -241,7 +269,6 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
 #pragma unroll
     for (int i = 0; i < RPW; ++i) acc[s][i] = (Tc)0;
 
-  double part0 = 0.0, part1 = 0.0;
   const int gxo = x0 + col;
   const bool colown = gxo < nx;
 
@@ -259,7 +286,7 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
       __syncthreads();
       if (k + PF < kend) fetch(k + PF, ph % PF);
       if (active) {
-        if constexpr (MODE == M_CG1) {
+        if constexpr (CG) {
           const int qs = ((k % QD) + QD) % QD;
 #pragma unroll
           for (int i = 0; i < RPW; ++i)
@@ -334,10 +361,16 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
               if (MODE == M_APPLY || MODE == M_RHS) {
                 if (a.nt_store) Io<Tout>::template st_nt<Tc>(a.out0, gi, val);
                 else Io<Tout>::template st<Tc>(a.out0, gi, val);
-              } else if (MODE == M_CG1) {
+              } else if (CG) {
                 if (a.nt_store) Io<Tout>::template st_nt<Tc>(a.out0, gi, val);
                 else Io<Tout>::template st<Tc>(a.out0, gi, val);
-                part0 = fma((double)cring[(qo * TY + wave * RPW + i) * TX + col], (double)val, part0);
+                const double qv = (double)val;
+                part0 = fma((double)cring[(qo * TY + wave * RPW + i) * TX + col], qv, part0);
+                if (FUSED) {
+                  const int ro = ((o % RQD) + RQD) % RQD;
+                  part1 = fma((double)rring[(ro * TY + wave * RPW + i) * TX + col], qv, part1);
+                  part2 = fma(qv, qv, part2);
+                }
               } else {
                 const double b = a.bvec[gi];
                 const double r = b - (double)val;
@@ -355,17 +388,22 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
     }
   }
 
-  if (MODE == M_CG1 || MODE == M_RESID) {
+  if (CG || MODE == M_RESID) {
     part0 = wave_sum(part0);
     part1 = wave_sum(part1);
-    if (lane == 0) { red[0][wv] = part0; red[1][wv] = part1; }
+    if (FUSED) {
+      part2 = wave_sum(part2);
+      part3 = wave_sum(part3);
+    }
+    if (lane == 0) { red[0][wv] = part0; red[1][wv] = part1; red[2][wv] = part2; red[3][wv] = part3; }
     __syncthreads();
     if (tid == 0) {
-      double s0 = 0.0, s1 = 0.0;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-      for (int q = 0; q < 4 * WX; ++q) { s0 += red[0][q]; s1 += red[1][q]; }
+      for (int q = 0; q < 4 * WX; ++q) { s0 += red[0][q]; s1 += red[1][q]; s2 += red[2][q]; s3 += red[3][q]; }
       a.part0[blockIdx.x] = s0;
-      if (MODE == M_RESID) a.part1[blockIdx.x] = s1;
+      if (MODE == M_RESID || FUSED) a.part1[blockIdx.x] = s1;
+      if (FUSED) { a.part2[blockIdx.x] = s2; a.part3[blockIdx.x] = s3; }
     }
   }
 }
@@ -446,6 +484,12 @@ hipError_t launch_cg1(const StencilArgs& a, int n, int bc, int dt, hipStream_t s
   if (dt == 0) return launch_n<M_CG1, double, double, double>(a, n, bc, st);
   if (dt == 1) return launch_n<M_CG1, float, float, float>(a, n, bc, st);
   if (dt == 2) return launch_n<M_CG1, uint16_t, float, float>(a, n, bc, st);
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_cgf(const StencilArgs& a, int n, int bc, int dt, hipStream_t st) {
+  if (dt == 1) return launch_n<M_CGF, float, float, float>(a, n, bc, st);
+  if (dt == 2) return launch_n<M_CGF, uint16_t, float, float>(a, n, bc, st);
   return hipErrorInvalidValue;
 }
 

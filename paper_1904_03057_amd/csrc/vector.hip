@@ -145,31 +145,39 @@ __global__ __launch_bounds__(256) void fill_kernel(uint32_t* __restrict__ x, int
 }
 
 __global__ __launch_bounds__(1024) void finalize_kernel(int op, const double* __restrict__ p0,
-                                                        const double* __restrict__ p1, int count, Scalars* s,
+                                                        const double* __restrict__ p1,
+                                                        const double* __restrict__ p2,
+                                                        const double* __restrict__ p3, int count, Scalars* s,
                                                         double rtol) {
-  __shared__ double r0[1024], r1[1024];
+  __shared__ double r0[1024], r1[1024], r2[1024], r3[1024];
   if (op == FIN_CLEAR_PENDING) {
     if (threadIdx.x == 0) s->pending = 0;
     return;
   }
-  if ((op == FIN_ALPHA || op == FIN_BETA) && s->done) return;
-  double a0 = 0.0, a1 = 0.0;
+  if ((op == FIN_ALPHA || op == FIN_BETA || op == FIN_FUSED) && s->done) return;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
   for (int i = threadIdx.x; i < count; i += 1024) {
     a0 += p0[i];
     if (p1) a1 += p1[i];
+    if (p2) a2 += p2[i];
+    if (p3) a3 += p3[i];
   }
   r0[threadIdx.x] = a0;
   r1[threadIdx.x] = a1;
+  r2[threadIdx.x] = a2;
+  r3[threadIdx.x] = a3;
   __syncthreads();
   for (int w = 512; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
       r0[threadIdx.x] += r0[threadIdx.x + w];
       r1[threadIdx.x] += r1[threadIdx.x + w];
+      r2[threadIdx.x] += r2[threadIdx.x + w];
+      r3[threadIdx.x] += r3[threadIdx.x + w];
     }
     __syncthreads();
   }
   if (threadIdx.x != 0) return;
-  const double v0 = r0[0], v1 = r1[0];
+  const double v0 = r0[0], v1 = r1[0], v2 = r2[0], v3 = r3[0];
   switch (op) {
     case FIN_INIT: {
       s->rr = v0; s->rr0 = v0; s->bb = v1; s->tol2 = rtol * rtol * v1;
@@ -193,6 +201,26 @@ __global__ __launch_bounds__(1024) void finalize_kernel(int op, const double* __
       s->nit += 1;
       s->pending = 1;
       if (v0 <= s->tol2) s->done = 1;
+      break;
+    }
+    case FIN_FUSED: {
+      // v0 = p_k.q_k, v1 = r_k.q_k, v2 = q_k.q_k, v3 = r_k.r_k of the iteration's recursive residual.
+      // alpha from the explicit r_k.r_k; r_{k+1}.r_{k+1} = r.r - 2 alpha r.q + alpha^2 q.q (one step
+      // ahead, restarted from the explicit value every iteration) gives beta and the stopping test.
+      s->pending = 0;
+      s->pq = v0;
+      if (!(v0 > 0.0) || !isfinite(v0) || !isfinite(v1) || !isfinite(v2) || !isfinite(v3)) {
+        s->status = -4; s->done = 1; break;
+      }
+      const double alpha = v3 / v0;
+      double rn = v3 - 2.0 * alpha * v1 + alpha * alpha * v2;
+      if (rn < 0.0) rn = 0.0;
+      s->alpha = alpha;
+      s->beta = v3 > 0.0 ? rn / v3 : 0.0;
+      s->rr = rn;
+      s->nit += 1;
+      s->pending = 1;
+      if (rn <= s->tol2) s->done = 1;
       break;
     }
     case FIN_DOT: s->out = v0; break;
@@ -283,8 +311,8 @@ hipError_t launch_fill(void* x, int dt, int64_t n, hipStream_t st) {
 }
 
 hipError_t launch_finalize(int op, const double* p0, const double* p1, int count, Scalars* s, double rtol,
-                           hipStream_t st) {
-  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, st, op, p0, p1, count, s, rtol);
+                           hipStream_t st, const double* p2, const double* p3) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(1), dim3(1024), 0, st, op, p0, p1, p2, p3, count, s, rtol);
   return hipGetLastError();
 }
 

@@ -55,15 +55,38 @@ def test_cg_step_continuation_bitwise():
     assert np.array_equal(host(x1), host(x2))
 
 
-def test_cg_fp32_iterates_close_to_oracle():
-    grid, n, h, tau, bc = (48, 20, 22), 3, (1 / 48, 1 / 20, 1 / 22), 1e-3, "dirichlet"
+@pytest.mark.parametrize("fused", [1, 0])
+@pytest.mark.parametrize("bc,grid", [("dirichlet", (48, 20, 22)), ("periodic", (64, 24, 20))])
+def test_cg_fp32_iterates_close_to_oracle(fused, bc, grid):
+    # both FP32 iteration forms (one kernel with the r.r prediction, two kernels) follow the oracle's
+    # Hestenes-Stiefel iterates and residual history to FP32 accuracy
+    n, tau = 3, 1e-3
+    h = tuple(1.0 / N for N in grid)
     b = rounded(normal_field(grid[::-1], 2), "f32")
     ctx = _ctx(grid, n, h, tau, bc, tbs.PREC_FP32)
+    ctx.set_opts(fused_cg=fused)
     x = dev(np.zeros(grid[::-1]), "f32")
     ctx.cg_begin(dev(b, "f32"), x, 0.0)
-    ctx.cg_step(8)
-    xr, _, _ = solvers.cg(lambda v: op.apply(v, n, h, tau, bc), b, np.zeros_like(b), 0.0, 100, fixed_iters=8)
+    rel, it = ctx.cg_step(8)
+    xr, _, hist = solvers.cg(lambda v: op.apply(v, n, h, tau, bc), b, np.zeros_like(b), 0.0, 100, fixed_iters=8)
+    assert it == 8
     assert np.linalg.norm(host(x) - xr) <= 1e-4 * np.linalg.norm(xr)
+    assert abs(rel - hist[-1]) <= 1e-3 * hist[-1], (rel, hist[-1])
+
+
+def test_cg_fp32_one_kernel_continuation_bitwise():
+    # r, p and q alternate between two arrays: splitting the iterations over calls changes nothing
+    grid, n, h, tau, bc = (40, 18, 20), 3, (1 / 40, 1 / 18, 1 / 20), 1e-3, "dirichlet"
+    b = dev(rounded(normal_field(grid[::-1], 5), "f32"), "f32")
+    ctx = _ctx(grid, n, h, tau, bc, tbs.PREC_FP32)
+    x1 = dev(np.zeros(grid[::-1]), "f32")
+    ctx.cg_begin(b, x1, 0.0)
+    ctx.cg_step(9)
+    x2 = dev(np.zeros(grid[::-1]), "f32")
+    ctx.cg_begin(b, x2, 0.0)
+    ctx.cg_step(4)
+    ctx.cg_step(5)
+    assert np.array_equal(host(x1), host(x2))
 
 
 def test_config1_fp64_step_matches_fft_exact_and_conserves():
@@ -100,14 +123,16 @@ def test_config1_tight_tolerance_reaches_1e10_error():
     assert np.linalg.norm(host(un) - xs) / np.linalg.norm(xs) <= 1e-10
 
 
-@pytest.mark.parametrize("prec", ["MIXED", "MIXED_BF16", "FP64"])
-def test_dirichlet_step_refined_matches_fdm_exact(prec):
+@pytest.mark.parametrize("prec,fused", [("MIXED", 1), ("MIXED_BF16", 1), ("MIXED", 0), ("MIXED_BF16", 0),
+                                        ("FP64", 1)])
+def test_dirichlet_step_refined_matches_fdm_exact(prec, fused):
     grid, n, tau = (48, 40, 36), 3, 1e-4
     h = tuple(1.0 / (N + 1) for N in grid)
     u0 = normal_field(grid[::-1], 21)
     q = normal_field(grid[::-1], 22) * 10
     p = getattr(tbs, "PREC_" + prec)
     ctx = _ctx(grid, n, h, tau, "dirichlet", p)
+    ctx.set_opts(fused_cg=fused)
     un = dev(np.zeros(grid[::-1]))
     st = ctx.timestep(dev(u0), dev(q), un, p, 1e-8, 2000)
     assert st["converged"], st
