@@ -120,7 +120,7 @@ def main():
     dname, (dms, dbytes, dcount) = dom
     achieved = dbytes / (dms / 1e3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None, "kernel": dname,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(dname), "kernel": dname,
                 "avg_launch_ms": round(dms / dcount, 4), "launches": dcount,
                 "algorithmic_bytes_per_launch": round(dbytes / dcount)}
 
@@ -144,6 +144,27 @@ def main():
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, params, out.get("s_per_step", {}))
     print(json.dumps(out), flush=True)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None when
+    there is none for it or the stencil sources have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "%s_heat928_traffic.txt" % kernel)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if "=" in line and not line.startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    h = hashlib.sha256()
+    for f in ("stencil.hip", "stencil.h", "common.h"):
+        with open(os.path.join(ROOT, "paper_1904_03057_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if kv.get("kernel") != kernel or kv.get("source_sha256") != h.hexdigest():
+        return None
+    return int(float(kv["traffic_bytes_per_launch"]))
 
 
 def probe(args):
