@@ -133,6 +133,9 @@ def main():
                    "global_batch": 1, "parallelism": "none"},
         "wall_s_timed": round(wall, 3),
         "iters_per_step": [s["iters"] for s in stats], "sweeps_per_step": [s["sweeps"] for s in stats],
+        "learned_guess_used": [s["used_learned_guess"] for s in stats],
+        "learned_over_plain_residual": [round(s["rel_res_learned"] / s["rel_res_plain"], 4)
+                                        if net is not None and s["rel_res_plain"] > 0 else None for s in stats],
         "rel_res_fp64": max(s["rel_res_fp64"] for s in stats),
         "roofline": roofline,
         "kernels": {k: {"ms": round(v[0], 3), "GB/s": round(v[1] / (v[0] / 1e3) / 1e9, 1), "launches": v[2]}
