@@ -23,8 +23,8 @@ sys.path.insert(0, ROOT)
 METRIC = "GDoF/s of (M+τΣK)u apply; s per implicit step at 0.8B DoF, learned vs plain CG"
 HBM_PEAK_GBS = 8000.0
 # network trained by paper_1904_03057_amd/train_guess.py on 128^3 windows at this workload's grid
-# spacing and time step (h = 1/929, tau = 1e-5)
-WEIGHTS = os.path.join(ROOT, "paper_1904_03057_amd", "weights", "guess_net_928w")
+# spacing and time step (h = 1/929, tau = 1e-5), half of the training trajectories without a source
+WEIGHTS = os.path.join(ROOT, "paper_1904_03057_amd", "weights", "guess_net_928z")
 
 
 def log(*a):

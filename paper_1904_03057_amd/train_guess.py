@@ -35,7 +35,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def fields(grid, h, seed, torch):
+def fields(grid, h, seed, torch, zero_source=False):
     import numpy as np
 
     import workloads
@@ -45,6 +45,8 @@ def fields(grid, h, seed, torch):
     pq = workloads.gaussian_params(seed + 31, int(rng.integers(1, 5)), 0.05, 0.15, 10.0, 0.1 * L, 0.9 * L)
     u = workloads.gaussian_sum(grid, "dirichlet", h, pu, xp=torch, device="cuda", dtype=torch.float64)
     q = workloads.gaussian_sum(grid, "dirichlet", h, pq, xp=torch, device="cuda", dtype=torch.float64)
+    if zero_source:
+        q.zero_()
     return u, q
 
 
@@ -64,7 +66,8 @@ def cmd_train(a):
     U, Q, D = [], [], []
     iters = []
     for t in range(a.traj):
-        u, q = fields(grid, h, 1000 + t, torch)
+        # the first zero_source_frac of the trajectories have no source (f = 0)
+        u, q = fields(grid, h, 1000 + t, torch, zero_source=t < int(round(a.zero_source_frac * a.traj)))
         for k in range(a.len):
             un = torch.empty_like(u)
             st = ctx.timestep(u, q, un, tbs.PREC_FP64, 1e-10, 2000)
@@ -117,6 +120,7 @@ def cmd_train(a):
     os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
     w.astype("<f4").tofile(a.out + ".f32")
     meta = {"grid": list(grid), "h": h[0], "tau": tau, "degree": 3, "bc": "dirichlet", "out_scale": out_scale,
+            "zero_source_frac": a.zero_source_frac,
             "lr": a.lr, "steps": a.steps, "batch": a.batch, "pairs": n_pairs, "train_pairs": int(len(train_idx)),
             "loss_first": [l for l in losses[:50] if l is not None][:5],
             "loss_last": [l for l in losses[-50:] if l is not None][-5:],
@@ -194,6 +198,8 @@ def main():
     t.add_argument("--batch", type=int, default=4)
     t.add_argument("--lr", type=float, default=1e-3)
     t.add_argument("--seed", type=int, default=5)
+    t.add_argument("--zero-source-frac", type=float, default=0.0,
+                   help="fraction of the training trajectories with f = 0")
     e = sub.add_parser("eval")
     e.add_argument("--weights", required=True)
     e.add_argument("--grid", type=int, default=512)
