@@ -74,6 +74,23 @@ def test_cg_fp32_iterates_close_to_oracle(fused, bc, grid):
     assert abs(rel - hist[-1]) <= 1e-3 * hist[-1], (rel, hist[-1])
 
 
+@pytest.mark.parametrize("n,grid,bc", [(1, (23, 17, 9), "dirichlet"), (2, (37, 11, 13), "periodic"),
+                                       (4, (45, 19, 21), "dirichlet"), (5, (70, 22, 24), "periodic")])
+def test_cg_fp32_one_kernel_other_degrees(n, grid, bc):
+    # ragged grids (not multiples of the tile or vector width) and the other basis degrees
+    tau = 2e-3
+    h = tuple(1.0 / N for N in grid)
+    b = rounded(normal_field(grid[::-1], 6 + n), "f32")
+    ctx = _ctx(grid, n, h, tau, bc, tbs.PREC_FP32)
+    x = dev(np.zeros(grid[::-1]), "f32")
+    ctx.cg_begin(dev(b, "f32"), x, 0.0)
+    rel, it = ctx.cg_step(6)
+    xr, _, hist = solvers.cg(lambda v: op.apply(v, n, h, tau, bc), b, np.zeros_like(b), 0.0, 100, fixed_iters=6)
+    assert it == 6
+    assert np.linalg.norm(host(x) - xr) <= 1e-4 * np.linalg.norm(xr)
+    assert abs(rel - hist[-1]) <= 1e-3 * hist[-1], (rel, hist[-1])
+
+
 def test_cg_fp32_one_kernel_continuation_bitwise():
     # r, p and q alternate between two arrays: splitting the iterations over calls changes nothing
     grid, n, h, tau, bc = (40, 18, 20), 3, (1 / 40, 1 / 18, 1 / 20), 1e-3, "dirichlet"
