@@ -270,6 +270,7 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N):
     res["apply"] = gd
     del y64, u32, y32, u16
     res["apply_degree_sweep"] = degree_sweep(tbs, torch)
+    res["transforms"] = transforms(tbs, torch, w, u0)
 
     def time_steps(prec, use_net, k):
         ua, ub = u0.clone(), torch.empty_like(u0)
@@ -339,6 +340,36 @@ def degree_sweep(tbs, torch):
         del ctx
     out["grid"] = list(w.grid)
     out["bc"] = w.bc
+    return out
+
+
+def transforms(tbs, torch, w, u0):
+    """Indirect transform (evaluation at the nodes, FP64) and direct transform (FP64 CG on the
+    evaluation operator to 1e-12, started from the samples) of the workload's field, cubic."""
+    N = w.grid[0] * w.grid[1] * w.grid[2]
+    t = tbs.Transform(w.grid, w.degree, w.bc)
+    t.ensure_workspace(tbs.PREC_FP64)
+    s = torch.empty_like(u0)
+    for _ in range(2):
+        t.eval(u0, s)
+    torch.cuda.synchronize()
+    t.prof_enable(True)
+    for _ in range(10):
+        t.eval(u0, s)
+    ms, by, cnt = list(t.prof_read().values())[0]
+    t.prof_enable(False)
+    c = s.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it, rel = t.interp(s, c, rtol=1e-12, max_iter=500)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    err = float(torch.linalg.vector_norm(c - u0) / torch.linalg.vector_norm(u0))
+    out = {"eval_f64": {"GDoF/s": round(N / (ms / cnt / 1e3) / 1e9, 1),
+                        "frac_hbm": round(by / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "ms": round(ms / cnt, 4)},
+           "interp_f64": {"s": round(dt, 4), "iters": it, "rel_res": rel, "rel_err_vs_coefficients": err}}
+    log("transforms: %s" % out)
+    del t, s, c
     return out
 
 

@@ -158,6 +158,34 @@ int tbs_cg_step(tbs_ctx* ctx, int n_iters, double* rel_res_out, int* iters_out);
 int tbs_timestep(tbs_ctx* ctx, const double* u_prev, const double* q, double* u_next, int prec,
                  double rtol, int max_iter, tbs_net* net, tbs_stats* stats);
 
+/* ------------------------------------------------------- B-spline transforms ------------- */
+/* Table 1 (interpolation row), Sec. 2.3 (Fig. figBspnSignProc) and Sec. 2.5 (method overview,
+ * steps 2 and 4): the indirect transform evaluates a spline at the grid nodes,
+ * s_k = sum_l c_l b^n(k - l) with the sampled B-spline b^n_k = beta^n(k), tensor product over the
+ * three axes; the direct transform inverts it, c = (b^n)^{-1} * s.  Same grid layout and boundary
+ * conditions as the operator: periodic = circular convolution, Dirichlet = coefficients outside
+ * the box are zero (truncated band).  The paper applies the inverse by recursive filtering; here
+ * the direct transform is the FP64 CG solve of E c = s with E applied on the fly (E is SPD with
+ * condition number below 8^3 for degrees 2..5), which reaches the same exact solution. */
+
+/* Creates a transform context for an Nx x Ny x Nz grid and spline degree 2..5 (each N_d >=
+ * 2 floor(degree/2) + 1), boundary condition bc, HIP stream.  tbs_destroy releases it;
+ * tbs_workspace_bytes / tbs_bind_workspace with TBS_PREC_FP64 size its solver workspace;
+ * tbs_apply and tbs_rhs on it also apply E; tbs_timestep refuses it (TBS_E_STATE). */
+int tbs_transform_setup(tbs_ctx** out, const int64_t grid[3], int degree, int bc, void* hip_stream);
+
+/* Indirect transform: samples = E coef.  dtype TBS_F64 or TBS_F32 for both arrays (device,
+ * 256-byte aligned, not aliased).  Asynchronous.  TBS_E_STATE on a solver context. */
+int tbs_transform_eval(tbs_ctx* ctx, const void* coef, void* samples, int dtype);
+
+/* Direct transform: solves E coef = samples in FP64 by CG, stopping when the recursive residual
+ * satisfies ||r|| <= rtol ||samples||, starting from the values coef holds on entry (a copy of the
+ * samples is a good start).  *iters and *rel_res (nullable) receive the CG iterations and the
+ * true FP64 relative residual recomputed at exit (near FP64 precision it can exceed rtol
+ * slightly).  Synchronises.  Returns TBS_OK, TBS_W_NOT_CONVERGED or TBS_E_BREAKDOWN. */
+int tbs_transform_interp(tbs_ctx* ctx, const double* samples, double* coef, double rtol, int max_iter,
+                         int* iters, double* rel_res);
+
 /* ------------------------------------------------------- learned initial guess ----------- */
 /* Not in the paper (which warm-starts CG from a coarse-grid solution).  A 3-D CNN
  * Conv(2->16) GELU Conv(16->16) GELU Conv(16->16) GELU Conv(16->1), 3x3x3 kernels, "same"

@@ -34,7 +34,7 @@ EXPORTS = [
     "tbs_timestep", "tbs_net_create", "tbs_net_destroy", "tbs_net_workspace_bytes", "tbs_net_bind_workspace",
     "tbs_net_set_weights", "tbs_net_get_weights", "tbs_net_set_hparams", "tbs_net_forward",
     "tbs_net_train_step", "tbs_net_conv_layer", "tbs_net_get_grad", "tbs_prof_enable", "tbs_prof_read", "tbs_strerror",
-    "tbs_last_error",
+    "tbs_last_error", "tbs_transform_setup", "tbs_transform_eval", "tbs_transform_interp",
 ]
 PROF_KINDS = ["apply_f64", "apply_f32", "apply_bf16_f32", "rhs_f64", "rhs_f32", "cg_fused_f64", "cg_fused_f32",
               "cg_fused_f32_bf16p", "residual_f64", "cg_update_f64", "cg_update_f32", "cg_iter_f32",
@@ -67,6 +67,10 @@ _lib.tbs_taps.argtypes = [_vp, _dp, _dp]
 _lib.tbs_set_opts.argtypes = [_vp, ctypes.POINTER(Opts)]
 _lib.tbs_apply.argtypes = [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int]
 _lib.tbs_rhs.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int]
+_lib.tbs_transform_setup.argtypes = [ctypes.POINTER(_vp), _i64p, ctypes.c_int, ctypes.c_int, _vp]
+_lib.tbs_transform_eval.argtypes = [_vp, _vp, _vp, ctypes.c_int]
+_lib.tbs_transform_interp.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
+                                      _dp]
 _lib.tbs_residual.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, _dp, _dp]
 _lib.tbs_dot.argtypes = [_vp, _vp, _vp, ctypes.c_int, _dp]
 _lib.tbs_convert.argtypes = [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int]
@@ -238,6 +242,34 @@ class Context:
         d = st.as_dict()
         d["converged"] = rc == OK
         return d
+
+
+class Transform(Context):
+    """Direct / indirect B-spline transforms of one grid, spline degree 2..5 and boundary condition."""
+
+    def __init__(self, grid, degree, bc, stream=None):
+        self._h = ctypes.c_void_p()
+        sh, self.stream = _stream_handle(stream)
+        g = (ctypes.c_int64 * 3)(*grid)
+        bcc = {"periodic": PERIODIC, "dirichlet": DIRICHLET}.get(bc, bc)
+        _check(_lib.tbs_transform_setup(ctypes.byref(self._h), g, degree, bcc, sh), "tbs_transform_setup")
+        self.grid, self.degree, self.h, self.tau, self.bc = tuple(grid), degree, (1.0, 1.0, 1.0), 0.0, bcc
+        self.shape = (grid[2], grid[1], grid[0])
+        self._ws = None
+
+    def eval(self, coef, samples):
+        """samples = E coef (indirect transform); FP64 or FP32 arrays of the grid's shape."""
+        _check(_lib.tbs_transform_eval(self._h, _ptr(coef), _ptr(samples), _dtype_code(samples)),
+               "tbs_transform_eval")
+
+    def interp(self, samples, coef, rtol=1e-13, max_iter=1000):
+        """Direct transform: solve E coef = samples (FP64) starting from coef; returns (iters, rel_res)."""
+        self.ensure_workspace(PREC_FP64)
+        it, rel = ctypes.c_int(), ctypes.c_double()
+        rc = _lib.tbs_transform_interp(self._h, _ptr(samples), _ptr(coef), rtol, max_iter, ctypes.byref(it),
+                                       ctypes.byref(rel))
+        _check(rc, "tbs_transform_interp", allow=(OK, W_NOT_CONVERGED))
+        return it.value, rel.value
 
 
 class Net:

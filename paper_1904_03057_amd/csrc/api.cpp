@@ -94,6 +94,7 @@ struct tbs_ctx {
   size_t ws_bytes;
   tbs_opts opts;
   Scalars* host_scal;  // pinned mirror, allocated on first solver call
+  int transform_degree;  // > 0: transform context (operator = sampled-B-spline evaluation filter)
   // CG session state (tbs_cg_begin / tbs_cg_step)
   int cg_active, cg_dt, cg_enq;
   void* cg_x;
@@ -215,6 +216,29 @@ extern "C" int tbs_setup(tbs_ctx** out, const int64_t grid[3], int degree, const
   c->opts.nt_store = 0;
   c->opts.fused_cg = 1;
   *out = c;
+  return TBS_OK;
+}
+
+// Transform context: the stencil kernels with half-width W = floor(degree / 2), mass taps replaced by
+// the sampled B-spline b^degree(k) and no stiffness, so the operator is the evaluation filter
+// E = Bx By Bz (Table 1 interpolation row; Sec. 2.3, Fig. figBspnSignProc).
+extern "C" int tbs_transform_setup(tbs_ctx** out, const int64_t grid[3], int degree, int bc, void* hip_stream) {
+  if (!out || !grid) return set_err(TBS_E_INVAL, "null argument");
+  *out = nullptr;
+  if (degree < 2 || degree > 5) return set_err(TBS_E_INVAL, "transform degree %d not in 2..5", degree);
+  const int W = degree / 2;
+  const double h1[3] = {1.0, 1.0, 1.0};
+  int rc = tbs_setup(out, grid, W, h1, 1.0, bc, hip_stream);
+  if (rc) return rc;
+  tbs_ctx* c = *out;
+  c->transform_degree = degree;
+  for (int k = 0; k < 6; ++k) {
+    c->taps.m[k] = k <= W ? bspline_val(degree, (double)k) : 0.0;
+    c->taps.s[k] = 0.0;
+  }
+  c->taps.ax = c->taps.ay = c->taps.az = 0.0;
+  c->taps.tau = 0.0;
+  c->tau = 0.0;
   return TBS_OK;
 }
 
@@ -612,6 +636,43 @@ extern "C" int tbs_cg_step(tbs_ctx* c, int n_iters, double* rel_res_out, int* it
 }
 
 // ------------------------------------------------------------------------------------------
+// B-spline transforms on a transform context
+
+extern "C" int tbs_transform_eval(tbs_ctx* c, const void* coef, void* samples, int dt) {
+  if (!c) return set_err(TBS_E_INVAL, "null context");
+  if (!c->transform_degree) return set_err(TBS_E_STATE, "not a transform context");
+  if (!coef) return set_err(TBS_E_INVAL, "null coefficients");
+  return tbs_rhs(c, coef, nullptr, samples, dt);  // E coef: the mass-only stencil with the evaluation taps
+}
+
+static int fp64_relres(tbs_ctx* c, const double* x, const double* b, double* rel);
+
+extern "C" int tbs_transform_interp(tbs_ctx* c, const double* samples, double* coef, double rtol, int max_iter,
+                                    int* iters, double* rel_res) {
+  if (!c) return set_err(TBS_E_INVAL, "null context");
+  if (!c->transform_degree) return set_err(TBS_E_STATE, "not a transform context");
+  if (!aligned_ptr(samples) || !aligned_ptr(coef)) return set_err(TBS_E_INVAL, "arrays must be 256-byte aligned device pointers");
+  if (samples == coef) return set_err(TBS_E_INVAL, "samples and coef must not alias");
+  if (!(rtol >= 0.0) || max_iter < 0) return set_err(TBS_E_INVAL, "bad rtol / max_iter");
+  int rc = need_ws(c, TBS_PREC_FP64);
+  if (rc) return rc;
+  c->cg_active = 0;
+  const Layout L = layout(c, TBS_PREC_FP64);
+  CgArrays A{coef, c->ws + L.off[1], {c->ws + L.off[2], c->ws + L.off[3]}, c->ws + L.off[4], nullptr, nullptr};
+  rc = cg_init_async(c, samples, A, 0, rtol);
+  if (rc) return rc;
+  int nit = 0;
+  const int result = cg_loop(c, A, 0, 0, max_iter, &nit);
+  if (result < 0 && result != TBS_E_BREAKDOWN) return result;
+  double rel = 0.0;
+  rc = fp64_relres(c, coef, samples, &rel);
+  if (rc) return rc;
+  if (iters) *iters = nit;
+  if (rel_res) *rel_res = rel;
+  return result;
+}
+
+// ------------------------------------------------------------------------------------------
 // implicit time step
 
 static int copy_async(tbs_ctx* c, void* dst, const void* src, size_t bytes) {
@@ -636,6 +697,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     return set_err(TBS_E_INVAL, "arrays must be 256-byte aligned device pointers");
   if (u_next == u_prev || u_next == q) return set_err(TBS_E_INVAL, "u_next must not alias the inputs");
   if (prec < TBS_PREC_FP64 || prec > TBS_PREC_MIXED_BF16) return set_err(TBS_E_INVAL, "bad precision mode");
+  if (c->transform_degree) return set_err(TBS_E_STATE, "tbs_timestep on a transform context");
   if (!(rtol >= 0.0) || max_iter < 0) return set_err(TBS_E_INVAL, "bad rtol / max_iter");
   int rc = need_ws(c, prec);
   if (rc) return rc;

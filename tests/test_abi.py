@@ -77,3 +77,23 @@ def test_calls_validate_pointers_before_hip():
     assert lib.tbs_bind_workspace(p, aligned, 16) == tbs.E_NOMEM
     assert lib.tbs_strerror(tbs.E_BREAKDOWN).startswith(b"CG breakdown")
     lib.tbs_destroy(p)
+
+
+def test_transform_setup_validation_without_gpu():
+    lib = tbs.lib()
+    p = ctypes.c_void_p()
+    g = (ctypes.c_int64 * 3)(16, 16, 16)
+    for deg in (0, 1, 6):
+        assert lib.tbs_transform_setup(ctypes.byref(p), g, deg, tbs.DIRICHLET, None) == tbs.E_INVAL and not p
+    small = (ctypes.c_int64 * 3)(16, 4, 16)  # degree 5: half-width 2 needs N_d >= 5
+    assert lib.tbs_transform_setup(ctypes.byref(p), small, 5, tbs.PERIODIC, None) == tbs.E_INVAL and not p
+    assert lib.tbs_transform_setup(ctypes.byref(p), g, 3, tbs.DIRICHLET, None) == tbs.OK and p
+    aligned = ctypes.c_void_p(1 << 20)
+    # a transform context refuses the time step, and the transform calls refuse a solver context
+    assert lib.tbs_timestep(p, aligned, None, ctypes.c_void_p(1 << 21), tbs.PREC_FP64, 1e-8, 10, None,
+                            None) == tbs.E_STATE
+    rc, s = _setup()
+    assert rc == tbs.OK
+    assert lib.tbs_transform_eval(s, aligned, ctypes.c_void_p(1 << 21), tbs.F64) == tbs.E_STATE
+    lib.tbs_destroy(s)
+    lib.tbs_destroy(p)
