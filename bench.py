@@ -295,6 +295,18 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N):
                     "rel_res_fp64": max(s["rel_res_fp64"] for s in sts),
                     "learned_used": [s["used_learned_guess"] for s in sts]}
         log("%s: %s" % (name, sp[name]))
+    # the paper's reduced-grid start: coarse-grid guess (halved grid, two-scale prolongation)
+    ctx.set_opts(poll_every=1, coarse_guess=1, coarse_rtol=1e-2)
+    for name, prec in (("refined_fp32_coarse", tbs.PREC_MIXED), ("plain_fp64_cg_coarse", tbs.PREC_FP64)):
+        ctx.ensure_workspace(prec)
+        t, sts = time_steps(prec, False, 2)
+        sp[name] = {"s_per_step": round(t, 4), "iters": [s["iters"] for s in sts],
+                    "rel_res_fp64": max(s["rel_res_fp64"] for s in sts),
+                    "coarse_used": [s["used_coarse_guess"] for s in sts],
+                    "coarse_iters": [s["coarse_iters"] for s in sts],
+                    "coarse_over_plain_residual": [round(s["rel_res_coarse"] / s["rel_res_plain"], 4) for s in sts]}
+        log("%s: %s" % (name, sp[name]))
+    ctx.set_opts(poll_every=1)
     res["s_per_step"] = sp
     if net is not None:
         du = torch.empty(u0.shape, dtype=torch.float32, device="cuda")

@@ -70,6 +70,9 @@ typedef struct {
   double rel_res0;         /* same for the chosen initial guess */
   double rel_res_plain;    /* same for the plain guess u^k */
   double rel_res_learned;  /* same for the network guess (NaN if no network) */
+  int used_coarse_guess;   /* 1 if the coarse-grid guess was kept by the fallback test */
+  int coarse_iters;        /* CG iterations of the coarse solve (0 if none) */
+  double rel_res_coarse;   /* FP64 relative residual of the coarse-grid guess (NaN if none) */
 } tbs_stats;
 
 typedef struct {
@@ -88,6 +91,16 @@ typedef struct {
                               prediction r.r - 2 alpha r.q + alpha^2 q.q; 0 = the two-kernel
                               Hestenes-Stiefel iteration (q = A p and p.q, then r -= alpha q and r.r).
                               The FP64 CG always uses the two-kernel form. */
+  int coarse_guess;        /* 1: tbs_timestep without a network starts from a coarse-grid guess
+                              (Sec. 3 leg example: CG started from a reduced-grid solution): the
+                              residual of u_prev is restricted to the halved grid, the coarse
+                              system (same tau, spacing 2h) is solved by FP64 CG to coarse_rtol,
+                              and its solution is prolongated by the two-scale relation and added;
+                              kept only if its FP64 residual is smaller than that of u_prev.  Odd
+                              degrees only (the coarse space nests in the fine one), periodic
+                              grids need even sizes, every coarse size >= 2n+1 (TBS_E_INVAL
+                              otherwise).  Enlarges tbs_workspace_bytes (default 0). */
+  double coarse_rtol;      /* relative tolerance of the coarse solve (default 1e-2) */
 } tbs_opts;
 
 /* ---------------------------------------------------------------- context ---------------- */

@@ -44,7 +44,9 @@ PROF_KINDS = ["apply_f64", "apply_f32", "apply_bf16_f32", "rhs_f64", "rhs_f32", 
 class Stats(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("sweeps", ctypes.c_int), ("used_learned_guess", ctypes.c_int),
                 ("status", ctypes.c_int), ("rel_res_fp64", ctypes.c_double), ("rel_res0", ctypes.c_double),
-                ("rel_res_plain", ctypes.c_double), ("rel_res_learned", ctypes.c_double)]
+                ("rel_res_plain", ctypes.c_double), ("rel_res_learned", ctypes.c_double),
+                ("used_coarse_guess", ctypes.c_int), ("coarse_iters", ctypes.c_int),
+                ("rel_res_coarse", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -53,7 +55,8 @@ class Stats(ctypes.Structure):
 class Opts(ctypes.Structure):
     _fields_ = [("inner_rtol", ctypes.c_double), ("inner_max_iter", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("poll_every", ctypes.c_int), ("zchunk", ctypes.c_int),
-                ("tile_order", ctypes.c_int), ("nt_store", ctypes.c_int), ("fused_cg", ctypes.c_int)]
+                ("tile_order", ctypes.c_int), ("nt_store", ctypes.c_int), ("fused_cg", ctypes.c_int),
+                ("coarse_guess", ctypes.c_int), ("coarse_rtol", ctypes.c_double)]
 
 
 _vp, _i64p, _dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
@@ -187,11 +190,16 @@ class Context:
         return list(m), list(s)
 
     def set_opts(self, inner_rtol=1e-4, inner_max_iter=500, max_sweeps=12, poll_every=4, zchunk=0,
-                 tile_order=0, nt_store=0, fused_cg=1):
-        o = Opts(inner_rtol, inner_max_iter, max_sweeps, poll_every, zchunk, tile_order, nt_store, fused_cg)
+                 tile_order=0, nt_store=0, fused_cg=1, coarse_guess=0, coarse_rtol=1e-2):
+        o = Opts(inner_rtol, inner_max_iter, max_sweeps, poll_every, zchunk, tile_order, nt_store, fused_cg,
+                 coarse_guess, coarse_rtol)
         _check(_lib.tbs_set_opts(self._h, ctypes.byref(o)), "tbs_set_opts")
-        if self._ws is not None and self._ws.numel() < self.workspace_bytes(-1):
-            self._ws = None
+        # options can change the workspace layout (partial-sum count, coarse-guess region): the
+        # library drops its binding then; rebind the buffer if it still holds the minimum
+        if self._ws is not None:
+            buf, self._ws = self._ws, None
+            if buf.numel() >= self.workspace_bytes(-1):
+                self.bind_workspace(buf)
 
     def apply(self, u, y):
         _check(_lib.tbs_apply(self._h, _ptr(u), _dtype_code(u), _ptr(y), _dtype_code(y)), "tbs_apply")

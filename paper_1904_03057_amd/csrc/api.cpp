@@ -15,6 +15,7 @@
 #include "common.h"
 #include "net.h"
 #include "stencil.h"
+#include "transfer.h"
 
 using namespace tbs;
 
@@ -95,6 +96,8 @@ struct tbs_ctx {
   tbs_opts opts;
   Scalars* host_scal;  // pinned mirror, allocated on first solver call
   int transform_degree;  // > 0: transform context (operator = sampled-B-spline evaluation filter)
+  tbs_ctx* coarse;       // coarse-grid guess: context of the halved grid (opts.coarse_guess)
+  int64_t cgrid[3];
   // CG session state (tbs_cg_begin / tbs_cg_step)
   int cg_active, cg_dt, cg_enq;
   void* cg_x;
@@ -136,7 +139,10 @@ static size_t ws_head(const tbs_ctx* c) { return 1024 + 4 * align256((size_t)c->
 struct Layout {
   size_t bytes;
   size_t off[8];
+  size_t coff[6];  // coarse-grid guess: FP64 r0, transfer temporaries T1, T2, coarse b, coarse x, coarse workspace
 };
+
+extern "C" size_t tbs_workspace_bytes(const tbs_ctx* c, int prec);
 
 static Layout layout(const tbs_ctx* c, int prec) {
   Layout L{};
@@ -153,6 +159,12 @@ static Layout layout(const tbs_ctx* c, int prec) {
       put(0, 8); put(1, 4); put(2, 4); put(3, 4); put(4, 4); put(5, 4); put(6, 4); put(7, 4); break;
     case TBS_PREC_MIXED_BF16:  // b64, r32, d, pA(bf16), pB(bf16), q, rB, qB
       put(0, 8); put(1, 4); put(2, 4); put(3, 2); put(4, 2); put(5, 4); put(6, 4); put(7, 4); break;
+  }
+  if (prec >= 0 && c->coarse) {
+    const size_t Nc = (size_t)(c->cgrid[0] * c->cgrid[1] * c->cgrid[2]);
+    const size_t t1 = (size_t)(c->cgrid[0] * c->ny * c->nz), t2 = (size_t)(c->cgrid[0] * c->cgrid[1] * c->nz);
+    const size_t sz[6] = {N * 8, t1 * 8, t2 * 8, Nc * 8, Nc * 8, tbs_workspace_bytes(c->coarse, TBS_PREC_FP64)};
+    for (int i = 0; i < 6; ++i) { L.coff[i] = o; o += align256(sz[i]); }
   }
   L.bytes = o;
   return L;
@@ -215,6 +227,8 @@ extern "C" int tbs_setup(tbs_ctx** out, const int64_t grid[3], int degree, const
   c->opts.tile_order = 0;
   c->opts.nt_store = 0;
   c->opts.fused_cg = 1;
+  c->opts.coarse_guess = 0;
+  c->opts.coarse_rtol = 1e-2;
   *out = c;
   return TBS_OK;
 }
@@ -244,6 +258,7 @@ extern "C" int tbs_transform_setup(tbs_ctx** out, const int64_t grid[3], int deg
 
 extern "C" void tbs_destroy(tbs_ctx* c) {
   if (!c) return;
+  if (c->coarse) tbs_destroy(c->coarse);
   if (c->host_scal) (void)hipHostFree(c->host_scal);
   for (auto& r : c->prof_pending) { (void)hipEventDestroy(r.e0); (void)hipEventDestroy(r.e1); }
   for (auto e : c->prof_pool) (void)hipEventDestroy(e);
@@ -345,12 +360,34 @@ extern "C" int tbs_set_opts(tbs_ctx* c, const tbs_opts* o) {
   if (!o) {
     c->opts.inner_rtol = 1e-4; c->opts.inner_max_iter = 500; c->opts.max_sweeps = 12; c->opts.poll_every = 4;
     c->opts.zchunk = 0; c->opts.tile_order = 0; c->opts.nt_store = 0; c->opts.fused_cg = 1;
+    c->opts.coarse_guess = 0; c->opts.coarse_rtol = 1e-2;
   } else {
     if (!(o->inner_rtol > 0 && o->inner_rtol < 1) || o->inner_max_iter < 1 || o->max_sweeps < 1 ||
         o->poll_every < 1 || o->zchunk < 0 || o->tile_order < 0 || o->tile_order > 1 || o->nt_store < 0 ||
-        o->nt_store > 1 || o->fused_cg < 0 || o->fused_cg > 1)
+        o->nt_store > 1 || o->fused_cg < 0 || o->fused_cg > 1 || o->coarse_guess < 0 || o->coarse_guess > 1 ||
+        !(o->coarse_rtol > 0 && o->coarse_rtol < 1))
       return set_err(TBS_E_INVAL, "bad options");
+    if (o->coarse_guess) {
+      if (c->transform_degree) return set_err(TBS_E_INVAL, "coarse guess on a transform context");
+      if (c->n % 2 == 0) return set_err(TBS_E_INVAL, "coarse guess needs an odd degree (nested dyadic spaces)");
+      const int64_t g[3] = {c->nx, c->ny, c->nz};
+      for (int d = 0; d < 3; ++d) {
+        if (c->bc == TBS_BC_PERIODIC && (g[d] & 1)) return set_err(TBS_E_INVAL, "periodic coarse guess needs even sizes");
+        if (g[d] / 2 < 2 * c->n + 1) return set_err(TBS_E_INVAL, "coarse grid[%d] = %lld < 2n+1", d, (long long)(g[d] / 2));
+      }
+    }
     c->opts = *o;
+  }
+  if (c->opts.coarse_guess && !c->coarse) {
+    const int64_t gc[3] = {c->nx / 2, c->ny / 2, c->nz / 2};
+    const double hc[3] = {2.0 * c->h[0], 2.0 * c->h[1], 2.0 * c->h[2]};
+    int rc = tbs_setup(&c->coarse, gc, c->n, hc, c->tau, c->bc, (void*)c->st);
+    if (rc) return rc;
+    for (int d = 0; d < 3; ++d) c->cgrid[d] = gc[d];
+    c->ws = nullptr;  // the workspace grows by the coarse region: rebind
+  } else if (!c->opts.coarse_guess && c->coarse) {
+    tbs_destroy(c->coarse);
+    c->coarse = nullptr;
   }
   // the partial-sum buffers are sized for the automatic geometry; a smaller chunk means more blocks
   const size_t old_head = ws_head(c);
@@ -706,6 +743,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
   const size_t N = (size_t)c->N;
   tbs_stats st{};
   st.rel_res_learned = NAN;
+  st.rel_res_coarse = NAN;
 
   // right-hand side, FP64 except for the raw FP32 path
   double* b64 = (prec == TBS_PREC_FP32) ? nullptr : (double*)(c->ws + L.off[0]);
@@ -751,6 +789,71 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     }
   }
 
+  if (!net && c->coarse && c->opts.coarse_guess && prec != TBS_PREC_FP32) {
+    // coarse-grid guess: u_next = u_prev + P d, A_c d = P^T (b - A u_prev) / 8
+    double* r0 = (double*)(c->ws + L.coff[0]);
+    double* t1 = (double*)(c->ws + L.coff[1]);
+    double* t2 = (double*)(c->ws + L.coff[2]);
+    double* bcv = (double*)(c->ws + L.coff[3]);
+    double* xc = (double*)(c->ws + L.coff[4]);
+    tbs_ctx* cc = c->coarse;
+    const int per = c->bc == TBS_BC_PERIODIC;
+    rc = resid_async(c, u_prev, b64, r0, TBS_F64, SC_AUX, FIN_NORMS, 0.0);
+    if (rc) return rc;
+    Scalars sp;
+    rc = read_scal(c, SC_AUX, &sp);
+    if (rc) return rc;
+    st.rel_res_plain = sp.out2 > 0 ? std::sqrt(sp.out / sp.out2) : std::sqrt(sp.out);
+    const int nx = (int)c->nx, ny = (int)c->ny, nz = (int)c->nz;
+    const int cx = (int)c->cgrid[0], cy = (int)c->cgrid[1], cz = (int)c->cgrid[2];
+    {  // restriction, 1/2 per axis (the Galerkin 1/8)
+      const int d1[3] = {cx, ny, nz}, d2[3] = {cx, cy, nz}, d3[3] = {cx, cy, cz};
+      HIPCHK(launch_transfer(r0, t1, d1, nx, 0, 0, per, c->n, 0.5, 0, c->st));
+      HIPCHK(launch_transfer(t1, t2, d2, ny, 1, 0, per, c->n, 0.5, 0, c->st));
+      HIPCHK(launch_transfer(t2, bcv, d3, nz, 2, 0, per, c->n, 0.5, 0, c->st));
+    }
+    rc = tbs_bind_workspace(cc, c->ws + L.coff[5], tbs_workspace_bytes(cc, TBS_PREC_FP64));
+    if (rc) return rc;
+    HIPCHK(launch_fill(xc, 0, cc->N, c->st));
+    const Layout Lc = layout(cc, TBS_PREC_FP64);
+    CgArrays Ac{xc, cc->ws + Lc.off[1], {cc->ws + Lc.off[2], cc->ws + Lc.off[3]}, cc->ws + Lc.off[4], nullptr, nullptr};
+    rc = cg_init_async(cc, bcv, Ac, 0, c->opts.coarse_rtol);
+    if (rc) return rc;
+    int cit = 0;
+    rc = cg_loop(cc, Ac, 0, 0, c->opts.inner_max_iter, &cit);
+    if (rc < 0 && rc != TBS_E_BREAKDOWN) return rc;
+    st.coarse_iters = cit;
+    {  // prolongation, added to u_next = u_prev
+      const int d1[3] = {cx, cy, nz}, d2[3] = {cx, ny, nz}, d3[3] = {nx, ny, nz};
+      HIPCHK(launch_transfer(xc, t2, d1, cz, 2, 1, per, c->n, 1.0, 0, c->st));
+      HIPCHK(launch_transfer(t2, t1, d2, cy, 1, 1, per, c->n, 1.0, 0, c->st));
+      HIPCHK(launch_transfer(t1, u_next, d3, cx, 0, 1, per, c->n, 1.0, 1, c->st));
+    }
+    if (prec == TBS_PREC_MIXED || prec == TBS_PREC_MIXED_BF16) {
+      // the guess's residual (FP32 copy and norms) is the first refinement sweep's when it is kept
+      rc = resid_async(c, u_next, b64, c->ws + L.off[1], TBS_F32, SC_AUX, FIN_NORMS, 0.0);
+      if (rc) return rc;
+      Scalars sg;
+      rc = read_scal(c, SC_AUX, &sg);
+      if (rc) return rc;
+      st.rel_res_coarse = sg.out2 > 0 ? std::sqrt(sg.out / sg.out2) : std::sqrt(sg.out);
+      if (st.rel_res_coarse < st.rel_res_plain) {
+        res0 = sg;
+        have_res0 = true;
+      }
+    } else {
+      rc = fp64_relres(c, u_next, b64, &st.rel_res_coarse);
+      if (rc) return rc;
+    }
+    if (st.rel_res_coarse < st.rel_res_plain) {
+      st.used_coarse_guess = 1;
+    } else {
+      rc = copy_async(c, u_next, u_prev, N * 8);
+      if (rc) return rc;
+      have_res0 = false;
+    }
+  }
+
   int result = TBS_OK;
   if (prec == TBS_PREC_FP64) {
     CgArrays A{u_next, c->ws + L.off[1], {c->ws + L.off[2], c->ws + L.off[3]}, c->ws + L.off[4], nullptr, nullptr};
@@ -760,7 +863,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     rc = read_scal(c, SC_CG, &s);
     if (rc) return rc;
     st.rel_res0 = s.bb > 0 ? std::sqrt(s.rr0 / s.bb) : 0.0;
-    if (!net) st.rel_res_plain = st.rel_res0;
+    if (!net && !st.used_coarse_guess && std::isnan(st.rel_res_coarse)) st.rel_res_plain = st.rel_res0;
     int nit = 0;
     result = cg_loop(c, A, 0, 0, max_iter, &nit);
     st.iters = nit;
@@ -816,7 +919,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
       const double rel = s.out2 > 0 ? std::sqrt(s.out / s.out2) : std::sqrt(s.out);
       if (sweeps == 0) {
         st.rel_res0 = rel;
-        if (!net) st.rel_res_plain = rel;
+        if (!net && std::isnan(st.rel_res_coarse)) st.rel_res_plain = rel;
       }
       st.rel_res_fp64 = rel;
       if (!std::isfinite(rel)) { result = set_err(TBS_E_BREAKDOWN, "non-finite residual"); break; }
