@@ -522,24 +522,6 @@ __global__ __launch_bounds__(256) void mse_grad(const float* __restrict__ o, con
   if (threadIdx.x == 0) part[blockIdx.x] = (red[0] + red[1]) + (red[2] + red[3]);
 }
 
-// One axis of the output low-pass filter: dst = [1/4, 1/2, 1/4] * src along `axis` (0 x, 1 y, 2 z),
-// zero outside a Dirichlet grid, wrapped on a periodic one.  Symmetric, so it is its own adjoint.
-__global__ __launch_bounds__(256) void smooth_axis(const float* __restrict__ src, float* __restrict__ dst, Grid3 g,
-                                                   int axis) {
-  const int64_t N = (int64_t)g.nx * g.ny * g.nz;
-  const int64_t stride = axis == 0 ? 1 : (axis == 1 ? (int64_t)g.nx : (int64_t)g.nx * g.ny);
-  const int n = axis == 0 ? g.nx : (axis == 1 ? g.ny : g.nz);
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < N; i += (int64_t)gridDim.x * 256) {
-    const int c = (int)((i / stride) % n);
-    float l = 0.f, r = 0.f;
-    if (c > 0) l = src[i - stride];
-    else if (g.periodic) l = src[i + (int64_t)(n - 1) * stride];
-    if (c < n - 1) r = src[i + stride];
-    else if (g.periodic) r = src[i - (int64_t)(n - 1) * stride];
-    dst[i] = 0.25f * l + 0.5f * src[i] + 0.25f * r;
-  }
-}
-
 // One full pass B = Bx By Bz of the binomial low-pass on a 32 x 8 x 8 output tile staged with a
 // one-voxel halo in LDS (the three separable passes share the tile).
 constexpr int SMX = 32, SMY = 8, SMZ = 8;

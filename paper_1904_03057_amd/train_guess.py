@@ -3,7 +3,7 @@
 Train (dataset from the library's FP64 implicit steps, 2000 Adam steps, batch 4):
     python paper_1904_03057_amd/train_guess.py train --out paper_1904_03057_amd/weights/guess_net_128
         [--grid 128] [--h 1/129] [--tau 1e-4] [--traj 40] [--len 10] [--steps 2000] [--batch 4]
-Evaluate learned vs plain guess over implicit steps (refined FP32 CG to 1e-8):
+Evaluate learned vs plain guess (and the coarse-grid guess) over implicit steps (refined FP32 CG to 1e-8):
     python paper_1904_03057_amd/train_guess.py eval --weights paper_1904_03057_amd/weights/guess_net_128
         [--grid 512] [--h 1/513] [--tau 1e-4] [--steps 50]
 
@@ -148,14 +148,15 @@ def cmd_eval(a):
     w = np.fromfile(a.weights + ".f32", dtype="<f4")
     stream = torch.cuda.current_stream()
     ctx = tbs.Context(grid, 3, h, tau, "dirichlet", stream=stream)
-    ctx.set_opts(poll_every=2)
-    ctx.ensure_workspace(tbs.PREC_MIXED)
     net = tbs.Net(stream=stream)
     net.ensure_workspace(grid, 1, False)
     net.set_weights(w)
     net.set_hparams(out_scale=meta["out_scale"])
     res = {}
-    for name, use in (("plain", False), ("learned", True)):
+    for name, use in (("plain", False), ("learned", True), ("coarse", False)):
+        # "coarse": the reduced-grid start (halved grid, two-scale prolongation) instead of a network
+        ctx.set_opts(poll_every=2, coarse_guess=1 if name == "coarse" else 0)
+        ctx.ensure_workspace(tbs.PREC_MIXED)
         u, q = fields(grid, h, a.seed, torch)
         un = torch.empty_like(u)
         ctx.timestep(u, q, un, tbs.PREC_MIXED, a.rtol, 5000, net if use else None)  # warm-up
@@ -167,20 +168,25 @@ def cmd_eval(a):
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t0)
             its.append(st["iters"])
-            used.append(st["used_learned_guess"])
+            used.append(st["used_learned_guess"] if name != "coarse" else st["used_coarse_guess"])
             if use:
                 ratios.append(st["rel_res_learned"] / st["rel_res_plain"])
+            elif name == "coarse":
+                ratios.append(st["rel_res_coarse"] / st["rel_res_plain"])
             u, un = un, u
         res[name] = {"iters_mean": float(np.mean(its)), "iters": its, "s_per_step_mean": float(np.mean(times)),
                      "s_total": float(np.sum(times)), "learned_used": int(np.sum(used)),
                      "res_ratio_mean": float(np.mean(ratios)) if ratios else None}
         log("%s: iters %.2f  s/step %.4f  used %d" % (name, res[name]["iters_mean"], res[name]["s_per_step_mean"],
                                                      res[name]["learned_used"]))
+    res["coarse"]["coarse_used"] = res["coarse"].pop("learned_used")
     out = {"grid": list(grid), "h": h[0], "tau": tau, "steps": a.steps, "rtol": a.rtol,
            "weights": os.path.basename(a.weights), "trained_on": {k: meta[k] for k in ("grid", "h", "tau")},
-           "plain": res["plain"], "learned": res["learned"],
+           "plain": res["plain"], "learned": res["learned"], "coarse": res["coarse"],
            "iters_saved_per_step": res["plain"]["iters_mean"] - res["learned"]["iters_mean"],
-           "speedup": res["plain"]["s_per_step_mean"] / res["learned"]["s_per_step_mean"]}
+           "speedup": res["plain"]["s_per_step_mean"] / res["learned"]["s_per_step_mean"],
+           "coarse_iters_saved_per_step": res["plain"]["iters_mean"] - res["coarse"]["iters_mean"],
+           "coarse_speedup": res["plain"]["s_per_step_mean"] / res["coarse"]["s_per_step_mean"]}
     print(json.dumps(out), flush=True)
 
 
