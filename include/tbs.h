@@ -76,7 +76,8 @@ typedef struct {
 } tbs_stats;
 
 typedef struct {
-  double inner_rtol;       /* refinement: inner relative tolerance (default 1e-4) */
+  double inner_rtol;       /* refinement: inner relative tolerance (default 1e-6, at least 1e-4 with a
+                              bf16-stored direction); a sweep asks for max(inner_rtol, rtol / (2 rel)) */
   int inner_max_iter;      /* refinement: inner iteration cap per sweep (default 500) */
   int max_sweeps;          /* refinement: sweep cap (default 12) */
   int poll_every;          /* CG iterations enqueued between host convergence polls (default 4) */

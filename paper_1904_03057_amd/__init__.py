@@ -189,7 +189,7 @@ class Context:
         _check(_lib.tbs_taps(self._h, m, s), "tbs_taps")
         return list(m), list(s)
 
-    def set_opts(self, inner_rtol=1e-4, inner_max_iter=500, max_sweeps=12, poll_every=4, zchunk=0,
+    def set_opts(self, inner_rtol=1e-6, inner_max_iter=500, max_sweeps=12, poll_every=4, zchunk=0,
                  tile_order=0, nt_store=0, fused_cg=1, coarse_guess=0, coarse_rtol=1e-2):
         o = Opts(inner_rtol, inner_max_iter, max_sweeps, poll_every, zchunk, tile_order, nt_store, fused_cg,
                  coarse_guess, coarse_rtol)
