@@ -45,7 +45,7 @@ def main():
                          "copy (f64->f32 conversion, the traffic calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (the design notes "
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (the design notes "
               "describe how the z-slab decomposition would shard); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.probe:
