@@ -115,8 +115,9 @@ int tbs_setup(tbs_ctx** out, const int64_t grid[3], int degree, const double h[3
 void tbs_destroy(tbs_ctx* ctx);
 
 /* Device scratch needed by the solver entry points for precision mode prec (tbs_prec), or, with
- * prec = -1, by tbs_apply / tbs_rhs / tbs_residual / tbs_dot only (partial sums).  The caller
- * allocates it (256-byte aligned) and binds it; the library never allocates device memory. */
+ * prec = -1, by tbs_residual / tbs_dot only (partial sums); tbs_apply and tbs_rhs need none.  The
+ * caller allocates it (256-byte aligned) and binds it; the library never allocates device memory.
+ * Options that change the layout (tbs_set_opts: z-chunk, coarse guess) drop the binding. */
 size_t tbs_workspace_bytes(const tbs_ctx* ctx, int prec);
 int tbs_bind_workspace(tbs_ctx* ctx, void* dev_ptr, size_t bytes);
 
@@ -130,11 +131,11 @@ int tbs_set_opts(tbs_ctx* ctx, const tbs_opts* opts);
 
 /* y = A u  (the system operator F(c), on-the-fly strategy of Sec. 2.5).
  * in_dtype / out_dtype: (F64,F64), (F32,F32), (BF16,F32), (F32,F64) or (BF16,F64); arithmetic
- * is FP64 when out is F64, FP32 otherwise.  Needs a bound workspace of >= tbs_workspace_bytes(-1). */
+ * is FP64 when out is F64, FP32 otherwise.  Needs no workspace. */
 int tbs_apply(tbs_ctx* ctx, const void* u, int in_dtype, void* y, int out_dtype);
 
 /* b = (Mx (x) My (x) Mz)(u_prev + tau q): right-hand side of one implicit Euler step.
- * q may be NULL (f = 0).  dtype F64 or F32 for all three arrays. */
+ * q may be NULL (f = 0).  dtype F64 or F32 for all three arrays.  Needs no workspace. */
 int tbs_rhs(tbs_ctx* ctx, const void* u_prev, const void* q, void* b, int dtype);
 
 /* FP64 residual norms: *rnorm = ||b - A x||_2, *bnorm = ||b||_2 (x, b FP64).  If r != NULL the
@@ -157,8 +158,9 @@ int tbs_convert(tbs_ctx* ctx, const void* src, int src_dtype, void* dst, int dst
  * caller-owned and must stay alive until the last tbs_cg_step.  Asynchronous. */
 int tbs_cg_begin(tbs_ctx* ctx, const void* b, void* x, int dtype, double rtol);
 
-/* Runs up to n_iters more Hestenes-Stiefel iterations (stops once ||r|| <= rtol ||b||, with r the
- * recursive residual), leaving x consistent.  If rel_res_out is not NULL it receives ||r||/||b||
+/* Runs up to n_iters more CG iterations (FP64: Hestenes-Stiefel in two kernels; F32: the form
+ * tbs_opts.fused_cg selects) and stops once ||r|| <= rtol ||b||, r being the recursive residual
+ * (F32 one-kernel form: its one-step prediction), leaving x consistent.  If rel_res_out is not NULL it receives ||r||/||b||
  * and iters_out the total iteration count (both synchronise).  Returns TBS_E_BREAKDOWN on
  * p^T A p <= 0 or non-finite values. */
 int tbs_cg_step(tbs_ctx* ctx, int n_iters, double* rel_res_out, int* iters_out);
