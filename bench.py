@@ -271,6 +271,7 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N):
     del y64, u32, y32, u16
     res["apply_degree_sweep"] = degree_sweep(tbs, torch)
     res["transforms"] = transforms(tbs, torch, w, u0)
+    res.update(workload_steps(tbs, torch))
 
     def time_steps(prec, use_net, k):
         ua, ub = u0.clone(), torch.empty_like(u0)
@@ -352,6 +353,76 @@ def degree_sweep(tbs, torch):
         del ctx
     out["grid"] = list(w.grid)
     out["bc"] = w.bc
+    return out
+
+
+def workload_steps(tbs, torch):
+    """The other step workloads: 256^3 Dirichlet with a Gaussian source (10 steps, plain FP64 CG
+    vs refined FP32; the arrays fit the 256 MB Infinity Cache, so this is a latency figure), and
+    the 1024 x 512 x 256 periodic grid for degrees 2, 3, 5 (20 refined FP32 steps each, with the
+    conservation of sum u that a periodic grid without source has)."""
+    import numpy as np
+
+    import workloads
+    out = {}
+    w = workloads.HEAT_256_DIRICHLET
+    ctx = tbs.Context(w.grid, w.degree, w.h, w.tau, w.bc)
+    ctx.set_opts(poll_every=1)
+    u = torch.from_numpy(workloads.uniform_field(w.grid[::-1], w.seed)).cuda()
+    t = torch.empty_like(u)
+    for _ in range(w.smooth_passes):
+        ctx.rhs(u, None, t)
+        u, t = t, u
+    q = workloads.gaussian_sum(w.grid, w.bc, w.h, workloads.source_256(w.seed), xp=torch, device="cuda",
+                               dtype=torch.float64)
+    r256 = {}
+    for name, prec in (("plain_fp64_cg", tbs.PREC_FP64), ("refined_fp32", tbs.PREC_MIXED)):
+        ctx.ensure_workspace(prec)
+        ua, ub = u.clone(), torch.empty_like(u)
+        ctx.timestep(ua, q, ub, prec, w.rtol, 5000)  # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, rr = [], []
+        for _ in range(w.steps):
+            st = ctx.timestep(ua, q, ub, prec, w.rtol, 5000)
+            its.append(st["iters"])
+            rr.append(st["rel_res_fp64"])
+            ua, ub = ub, ua
+        torch.cuda.synchronize()
+        r256[name] = {"s_per_step": round((time.perf_counter() - t0) / w.steps, 5), "iters": its,
+                      "rel_res_fp64_max": max(rr)}
+    out["heat256_dirichlet_10_steps"] = r256
+    log("heat256: %s" % r256)
+    del ctx, u, t, q
+    w = workloads.HEAT_1024x512x256_PERIODIC
+    g = torch.Generator(device="cuda")
+    g.manual_seed(w.seed)
+    u0 = torch.randn(w.grid[::-1], generator=g, device="cuda", dtype=torch.float64)
+    r4 = {}
+    for n in w.degrees:
+        ctx = tbs.Context(w.grid, n, w.h, w.tau, w.bc)
+        ctx.set_opts(poll_every=1)
+        ctx.ensure_workspace(tbs.PREC_MIXED)
+        ua, ub = u0.clone(), torch.empty_like(u0)
+        for _ in range(w.smooth_passes):
+            ctx.rhs(ua, None, ub)
+            ua, ub = ub, ua
+        s0, a0 = float(ua.sum()), float(ua.abs().sum())
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, rr = [], []
+        for _ in range(w.steps):
+            st = ctx.timestep(ua, None, ub, tbs.PREC_MIXED, w.rtol, 5000)
+            its.append(st["iters"])
+            rr.append(st["rel_res_fp64"])
+            ua, ub = ub, ua
+        torch.cuda.synchronize()
+        r4["n%d" % n] = {"s_per_step": round((time.perf_counter() - t0) / w.steps, 5),
+                         "iters_first_last": [its[0], its[-1]], "rel_res_fp64_max": max(rr),
+                         "sum_u_drift_rel": abs(float(ua.sum()) - s0) / a0}
+        del ctx
+    out["heat1024x512x256_periodic_20_steps"] = r4
+    log("heat1024x512x256: %s" % r4)
     return out
 
 

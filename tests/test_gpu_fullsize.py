@@ -131,3 +131,24 @@ def test_apply_periodic_1024x512x256_sampled(n):
     got = y[tuple(torch.from_numpy(pts.T).cuda())].to(torch.float64).cpu().numpy()
     tol = op_tolerance(n, "f32", scale) + np.abs(ref) * 2.0 ** -24
     assert np.all(np.abs(got - ref) <= tol)
+
+
+def test_periodic_1024x512x256_refined_steps_converge_and_conserve():
+    # two refined FP32 steps of the cubic periodic workload: FP64 residual <= rtol and, with no
+    # source on a periodic grid, sum u is conserved up to the residual (|sum r| <= sqrt(N) ||r||)
+    w = workloads.HEAT_1024x512x256_PERIODIC
+    g = torch.Generator(device="cuda")
+    g.manual_seed(w.seed)
+    u = torch.randn(w.grid[::-1], generator=g, device="cuda", dtype=torch.float64)
+    ctx = tbs.Context(w.grid, 3, w.h, w.tau, w.bc)
+    ctx.ensure_workspace(tbs.PREC_MIXED)
+    t = torch.empty_like(u)
+    for _ in range(w.smooth_passes):
+        ctx.rhs(u, None, t)
+        u, t = t, u
+    s0, a0 = float(u.sum()), float(u.abs().sum())
+    for _ in range(2):
+        st = ctx.timestep(u, None, t, tbs.PREC_MIXED, w.rtol, 2000)
+        assert st["converged"] and st["rel_res_fp64"] <= w.rtol
+        u, t = t, u
+    assert abs(float(u.sum()) - s0) <= 1e-7 * a0
