@@ -149,6 +149,10 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+# the sources of the stencil kernels: a traffic summary holds only while they hash as measured
+STENCIL_SOURCES = ("stencil_kernel.h", "stencil.hip", "stencil.h", "common.h")
+
+
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None when
     there is none for it or the stencil sources have changed since the counters were taken."""
@@ -162,7 +166,7 @@ def measured_traffic(kernel):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
     h = hashlib.sha256()
-    for f in ("stencil.hip", "stencil.h", "common.h"):
+    for f in STENCIL_SOURCES:
         with open(os.path.join(ROOT, "paper_1904_03057_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     if kv.get("kernel") != kernel or kv.get("source_sha256") != h.hexdigest():

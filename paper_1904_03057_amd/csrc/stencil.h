@@ -35,6 +35,11 @@ constexpr int stencil_tile_y(int mode, int compute_bytes) {
   return compute_bytes == 4 ? ((mode == M_APPLY) ? 32 : (mode == M_CG1 ? STENCIL_CG_TY : (mode == M_CGF ? STENCIL_CGF_TY : 16)))
                             : (mode == M_RESID ? STENCIL_RESID_TY : 16);
 }
+// One stencil launch of degree N for a (mode, input, compute, output) type combination; defined
+// in stencil_kernel.h and instantiated per degree in stencil_n<N>.hip.
+template <int N, int MODE, typename Tin, typename Tc, typename Tout>
+hipError_t launch_bc(const StencilArgs& a, int bc, bool vec, hipStream_t st);
+
 // Number of workgroups (= partial sums written) of a stencil launch of this mode.
 int stencil_blocks(const StencilArgs& a, int mode, int compute_bytes);
 

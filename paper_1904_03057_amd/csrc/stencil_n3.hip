@@ -1,0 +1,4 @@
+// Stencil kernels of basis degree 3 (one translation unit per degree).
+#include "stencil_kernel.h"
+
+TBS_STENCIL_INSTANTIATE(3)
