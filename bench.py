@@ -2,7 +2,8 @@
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload heat928] [--no-cpu-baseline]
 
-A step is one implicit Euler step of the whole hot path on the 928^3 cubic Dirichlet workload
+K defaults to the workload's own step count (100 implicit steps at 928^3).  A step is one
+implicit Euler step of the whole hot path on the 928^3 cubic Dirichlet workload
 (~0.8e9 DoF): right-hand side, initial guess (network guess with FP64 fallback test when
 trained weights are present, else u^k), FP64-refined FP32 CG to a relative residual of 1e-8.
 value = DoF advanced per second (GDoF/s of implicit stepping, inputs resident in HBM).
@@ -34,7 +35,7 @@ def log(*a):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=None, help="default: the workload's step count")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="heat928")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -49,6 +50,8 @@ def main():
               "describe how the z-slab decomposition would shard); use --gpus 1", file=sys.stderr)
         sys.exit(2)
     if args.probe:
+        if args.steps is None:
+            args.steps = 5
         probe(args)
         return
 
@@ -60,6 +63,8 @@ def main():
 
     w = {"heat928": workloads.HEAT_928_DIRICHLET, "heat256": workloads.HEAT_256_DIRICHLET,
          "heat512": workloads.HEAT_512_EVAL}[args.workload]
+    if args.steps is None:
+        args.steps = w.steps
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
     N = w.grid[0] * w.grid[1] * w.grid[2]
@@ -143,7 +148,7 @@ def main():
     }
 
     if not args.no_extras:
-        out.update(extras(ctx, tbs, torch, w, u0, stream, net, N))
+        out.update(extras(ctx, tbs, torch, w, u0, stream, net, N, args.steps))
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, params, out.get("s_per_step", {}))
     print(json.dumps(out), flush=True)
@@ -232,7 +237,7 @@ def probe(args):
                       "avg_ms": (ms / args.steps) if ms else None}), flush=True)
 
 
-def extras(ctx, tbs, torch, w, u0, stream, net, N):
+def extras(ctx, tbs, torch, w, u0, stream, net, N, k_all):
     """Apply throughput per dtype and seconds per step of the other solver variants."""
     res = {}
     with torch.cuda.stream(stream):
@@ -313,6 +318,27 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N):
         log("%s: %s" % (name, sp[name]))
     ctx.set_opts(poll_every=1)
     res["s_per_step"] = sp
+    # the same k_all steps as the timed run, from the same field: plain FP64 CG, refined FP32 with
+    # the plain guess, and refined FP32 with the network under the backoff policy (a rejected
+    # network is skipped for 1, 2, 4, ... steps before it is tested again)
+    allv = [("plain_fp64_cg", tbs.PREC_FP64, False), ("refined_fp32", tbs.PREC_MIXED, False)]
+    if net is not None:
+        allv.append(("refined_fp32_learned_backoff", tbs.PREC_MIXED, True))
+    ra = {}
+    for name, prec, use_net in allv:
+        ctx.set_opts(poll_every=1, guess_backoff=1 if use_net else 0)
+        ctx.ensure_workspace(prec)
+        t, sts = time_steps(prec, use_net, k_all)
+        ra[name] = {"s_per_step": round(t, 4), "iters_total": sum(s["iters"] for s in sts),
+                    "iters_first_last": [sts[0]["iters"], sts[-1]["iters"]],
+                    "rel_res_fp64_max": max(s["rel_res_fp64"] for s in sts)}
+        if use_net:
+            ra[name]["net_runs"] = sum(1 - s["skipped_learned_guess"] for s in sts)
+            ra[name]["net_kept"] = sum(s["used_learned_guess"] for s in sts)
+        log("%d steps %s: %s" % (k_all, name, ra[name]))
+    ctx.set_opts(poll_every=1)
+    ctx.ensure_workspace(tbs.PREC_MIXED)
+    res["all_%d_steps" % k_all] = ra
     if net is not None:
         du = torch.empty(u0.shape, dtype=torch.float32, device="cuda")
         for _ in range(2):

@@ -73,6 +73,7 @@ typedef struct {
   int used_coarse_guess;   /* 1 if the coarse-grid guess was kept by the fallback test */
   int coarse_iters;        /* CG iterations of the coarse solve (0 if none) */
   double rel_res_coarse;   /* FP64 relative residual of the coarse-grid guess (NaN if none) */
+  int skipped_learned_guess;  /* 1 if a network was passed but not run this step (guess_backoff) */
 } tbs_stats;
 
 typedef struct {
@@ -102,6 +103,11 @@ typedef struct {
                               grids need even sizes, every coarse size >= 2n+1 (TBS_E_INVAL
                               otherwise).  Enlarges tbs_workspace_bytes (default 0). */
   double coarse_rtol;      /* relative tolerance of the coarse solve (default 1e-2) */
+  int guess_backoff;       /* tbs_timestep with a network: 0 = run and test the network guess on
+                              every step (default); 1 = after the k-th consecutive rejection, skip
+                              the network for the next min(2^(k-1), 64) steps (plain guess, no
+                              network cost), then test it again; a kept guess resets k.  The
+                              counters live in the context; tbs_set_opts resets them. */
 } tbs_opts;
 
 /* ---------------------------------------------------------------- context ---------------- */
@@ -170,7 +176,8 @@ int tbs_cg_step(tbs_ctx* ctx, int n_iters, double* rel_res_out, int* iters_out);
 /* One implicit Euler step: solves A u_next = M (u_prev + tau q) to ||b - A u|| <= rtol ||b||.
  * u_prev, q (nullable), u_next: FP64 device arrays.  prec selects the arithmetic (tbs_prec).
  * net: optional learned initial guess; its guess is kept only if its FP64 residual is smaller
- * than that of the plain guess u_prev.  Synchronises; fills *stats if not NULL. */
+ * than that of the plain guess u_prev (tbs_opts.guess_backoff: whether a rejected network is
+ * skipped on the following steps).  Synchronises; fills *stats if not NULL. */
 int tbs_timestep(tbs_ctx* ctx, const double* u_prev, const double* q, double* u_next, int prec,
                  double rtol, int max_iter, tbs_net* net, tbs_stats* stats);
 

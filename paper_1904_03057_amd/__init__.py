@@ -46,7 +46,7 @@ class Stats(ctypes.Structure):
                 ("status", ctypes.c_int), ("rel_res_fp64", ctypes.c_double), ("rel_res0", ctypes.c_double),
                 ("rel_res_plain", ctypes.c_double), ("rel_res_learned", ctypes.c_double),
                 ("used_coarse_guess", ctypes.c_int), ("coarse_iters", ctypes.c_int),
-                ("rel_res_coarse", ctypes.c_double)]
+                ("rel_res_coarse", ctypes.c_double), ("skipped_learned_guess", ctypes.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -56,7 +56,7 @@ class Opts(ctypes.Structure):
     _fields_ = [("inner_rtol", ctypes.c_double), ("inner_max_iter", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("poll_every", ctypes.c_int), ("zchunk", ctypes.c_int),
                 ("tile_order", ctypes.c_int), ("nt_store", ctypes.c_int), ("fused_cg", ctypes.c_int),
-                ("coarse_guess", ctypes.c_int), ("coarse_rtol", ctypes.c_double)]
+                ("coarse_guess", ctypes.c_int), ("coarse_rtol", ctypes.c_double), ("guess_backoff", ctypes.c_int)]
 
 
 _vp, _i64p, _dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
@@ -190,9 +190,9 @@ class Context:
         return list(m), list(s)
 
     def set_opts(self, inner_rtol=1e-6, inner_max_iter=500, max_sweeps=12, poll_every=4, zchunk=0,
-                 tile_order=0, nt_store=0, fused_cg=1, coarse_guess=0, coarse_rtol=1e-2):
+                 tile_order=0, nt_store=0, fused_cg=1, coarse_guess=0, coarse_rtol=1e-2, guess_backoff=0):
         o = Opts(inner_rtol, inner_max_iter, max_sweeps, poll_every, zchunk, tile_order, nt_store, fused_cg,
-                 coarse_guess, coarse_rtol)
+                 coarse_guess, coarse_rtol, guess_backoff)
         _check(_lib.tbs_set_opts(self._h, ctypes.byref(o)), "tbs_set_opts")
         # options can change the workspace layout (partial-sum count, coarse-guess region): the
         # library drops its binding then; rebind the buffer if it still holds the minimum

@@ -98,6 +98,8 @@ struct tbs_ctx {
   int transform_degree;  // > 0: transform context (operator = sampled-B-spline evaluation filter)
   tbs_ctx* coarse;       // coarse-grid guess: context of the halved grid (opts.coarse_guess)
   int64_t cgrid[3];
+  // learned-guess backoff (opts.guess_backoff): consecutive rejections, steps left to skip
+  int guess_rejects, guess_wait;
   // CG session state (tbs_cg_begin / tbs_cg_step)
   int cg_active, cg_dt, cg_enq;
   void* cg_x;
@@ -360,12 +362,12 @@ extern "C" int tbs_set_opts(tbs_ctx* c, const tbs_opts* o) {
   if (!o) {
     c->opts.inner_rtol = 1e-6; c->opts.inner_max_iter = 500; c->opts.max_sweeps = 12; c->opts.poll_every = 4;
     c->opts.zchunk = 0; c->opts.tile_order = 0; c->opts.nt_store = 0; c->opts.fused_cg = 1;
-    c->opts.coarse_guess = 0; c->opts.coarse_rtol = 1e-2;
+    c->opts.coarse_guess = 0; c->opts.coarse_rtol = 1e-2; c->opts.guess_backoff = 0;
   } else {
     if (!(o->inner_rtol > 0 && o->inner_rtol < 1) || o->inner_max_iter < 1 || o->max_sweeps < 1 ||
         o->poll_every < 1 || o->zchunk < 0 || o->tile_order < 0 || o->tile_order > 1 || o->nt_store < 0 ||
         o->nt_store > 1 || o->fused_cg < 0 || o->fused_cg > 1 || o->coarse_guess < 0 || o->coarse_guess > 1 ||
-        !(o->coarse_rtol > 0 && o->coarse_rtol < 1))
+        !(o->coarse_rtol > 0 && o->coarse_rtol < 1) || o->guess_backoff < 0 || o->guess_backoff > 1)
       return set_err(TBS_E_INVAL, "bad options");
     if (o->coarse_guess) {
       if (c->transform_degree) return set_err(TBS_E_INVAL, "coarse guess on a transform context");
@@ -378,6 +380,7 @@ extern "C" int tbs_set_opts(tbs_ctx* c, const tbs_opts* o) {
     }
     c->opts = *o;
   }
+  c->guess_rejects = c->guess_wait = 0;
   if (c->opts.coarse_guess && !c->coarse) {
     const int64_t gc[3] = {c->nx / 2, c->ny / 2, c->nz / 2};
     const double hc[3] = {2.0 * c->h[0], 2.0 * c->h[1], 2.0 * c->h[2]};
@@ -745,14 +748,19 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
   st.rel_res_learned = NAN;
   st.rel_res_coarse = NAN;
 
-  // right-hand side, FP64 except for the raw FP32 path
+  // right-hand side, FP64 except for the raw FP32 path (which builds its FP64 b after the solve)
   double* b64 = (prec == TBS_PREC_FP32) ? nullptr : (double*)(c->ws + L.off[0]);
-  double* b64_tmp = nullptr;
   if (prec != TBS_PREC_FP32) {
     rc = tbs_rhs(c, u_prev, q, b64, TBS_F64);
     if (rc) return rc;
-  } else {
-    // the FP64 check needs an FP64 b: keep it in u_next temporarily? no -- compute b64 on demand below
+  }
+
+  // the network is run unless the backoff policy is waiting out an earlier rejection
+  tbs_net* g = (prec != TBS_PREC_FP32) ? net : nullptr;
+  if (g && c->opts.guess_backoff && c->guess_wait > 0) {
+    --c->guess_wait;
+    g = nullptr;
+    st.skipped_learned_guess = 1;
   }
 
   // initial guess: plain u^k, or the network guess if its FP64 residual is smaller
@@ -762,10 +770,10 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
   // refinement sweep's residual whenever the plain guess is kept, so it is computed last and reused
   bool have_res0 = false;
   Scalars res0{};
-  if (net && prec != TBS_PREC_FP32) {
+  if (g) {
     const float* du = nullptr;
     const int64_t grid[3] = {c->nx, c->ny, c->nz};
-    rc = tbs_net_guess_internal(net, grid, c->bc == TBS_BC_PERIODIC, c->tau, c->st, u_prev, q, &du);
+    rc = tbs_net_guess_internal(g, grid, c->bc == TBS_BC_PERIODIC, c->tau, c->st, u_prev, q, &du);
     if (rc) return rc;
     HIPCHK(launch_guess_combine(u_next, u_prev, du, c->N, c->st));
     rc = fp64_relres(c, u_next, b64, &st.rel_res_learned);
@@ -782,14 +790,17 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     }
     if (st.rel_res_learned < st.rel_res_plain) {
       st.used_learned_guess = 1;
+      c->guess_rejects = 0;
     } else {
       rc = copy_async(c, u_next, u_prev, N * 8);
       if (rc) return rc;
       have_res0 = (prec == TBS_PREC_MIXED || prec == TBS_PREC_MIXED_BF16);
+      ++c->guess_rejects;
+      if (c->opts.guess_backoff) c->guess_wait = 1 << std::min(c->guess_rejects - 1, 6);
     }
   }
 
-  if (!net && c->coarse && c->opts.coarse_guess && prec != TBS_PREC_FP32) {
+  if (!g && c->coarse && c->opts.coarse_guess && prec != TBS_PREC_FP32) {
     // coarse-grid guess: u_next = u_prev + P d, A_c d = P^T (b - A u_prev) / 8
     double* r0 = (double*)(c->ws + L.coff[0]);
     double* t1 = (double*)(c->ws + L.coff[1]);
@@ -863,7 +874,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     rc = read_scal(c, SC_CG, &s);
     if (rc) return rc;
     st.rel_res0 = s.bb > 0 ? std::sqrt(s.rr0 / s.bb) : 0.0;
-    if (!net && !st.used_coarse_guess && std::isnan(st.rel_res_coarse)) st.rel_res_plain = st.rel_res0;
+    if (!g && !st.used_coarse_guess && std::isnan(st.rel_res_coarse)) st.rel_res_plain = st.rel_res0;
     int nit = 0;
     result = cg_loop(c, A, 0, 0, max_iter, &nit);
     st.iters = nit;
@@ -894,7 +905,6 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     HIPCHK(launch_convert(x32, 1, u_next, 0, c->N, c->st));
     // FP64 residual of the FP32 answer against the FP64 right-hand side (b64 built in r-space)
     double* b64w = (double*)(c->ws + L.off[2]);  // r32 + pA span >= 8N bytes: reuse as FP64 b
-    (void)b64_tmp;
     rc = tbs_rhs(c, u_prev, q, b64w, TBS_F64);
     if (rc) return rc;
     rc = fp64_relres(c, u_next, b64w, &st.rel_res_fp64);
@@ -919,7 +929,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
       const double rel = s.out2 > 0 ? std::sqrt(s.out / s.out2) : std::sqrt(s.out);
       if (sweeps == 0) {
         st.rel_res0 = rel;
-        if (!net && std::isnan(st.rel_res_coarse)) st.rel_res_plain = rel;
+        if (!g && std::isnan(st.rel_res_coarse)) st.rel_res_plain = rel;
       }
       st.rel_res_fp64 = rel;
       if (!std::isfinite(rel)) { result = set_err(TBS_E_BREAKDOWN, "non-finite residual"); break; }

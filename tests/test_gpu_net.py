@@ -188,3 +188,38 @@ def test_fallback_keeps_plain_path_with_useless_net():
     assert s1["used_learned_guess"] == 0 and s1["rel_res_learned"] > s1["rel_res_plain"]
     assert np.array_equal(host(a), host(b))
     assert s1["iters"] == s0["iters"]
+
+
+def test_guess_backoff_skips_a_rejected_net():
+    # guess_backoff = 1: after the k-th consecutive rejection the network is skipped for
+    # min(2^(k-1), 64) steps; skipped steps take the plain path (bitwise) with no network cost
+    grid, n, tau = (32, 24, 20), 3, 1e-3
+    h = tuple(1.0 / (N + 1) for N in grid)
+    u = dev(normal_field(grid[::-1], 3))
+    theta = cnn_init(1)
+    theta[cnn.N_PARAMS - 1] = 100.0   # the guess adds a large constant: always rejected
+    net = tbs.Net()
+    net.ensure_workspace(grid, 1, False)
+    net.set_weights(theta)
+    ctx = tbs.Context(grid, n, h, tau, "dirichlet")
+    ctx.ensure_workspace(tbs.PREC_MIXED)
+    b = dev(np.zeros(grid[::-1]))
+    ctx.timestep(u, None, b, tbs.PREC_MIXED, 1e-8, 500, None)
+    ref = host(b)
+    ctx.set_opts(guess_backoff=1)
+    ctx.ensure_workspace(tbs.PREC_MIXED)
+    skipped = []
+    for _ in range(11):
+        a = dev(np.zeros(grid[::-1]))
+        s = ctx.timestep(u, None, a, tbs.PREC_MIXED, 1e-8, 500, net)
+        assert s["used_learned_guess"] == 0
+        assert np.isnan(s["rel_res_learned"]) == bool(s["skipped_learned_guess"])
+        assert np.array_equal(host(a), ref)
+        skipped.append(s["skipped_learned_guess"])
+    assert skipped == [0, 1, 0, 1, 1, 0, 1, 1, 1, 1, 0]
+    # set_opts resets the counters; with backoff off the network runs on every step
+    ctx.set_opts(guess_backoff=0)
+    ctx.ensure_workspace(tbs.PREC_MIXED)
+    for _ in range(3):
+        s = ctx.timestep(u, None, a, tbs.PREC_MIXED, 1e-8, 500, net)
+        assert s["skipped_learned_guess"] == 0 and not np.isnan(s["rel_res_learned"])
