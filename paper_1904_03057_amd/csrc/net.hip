@@ -524,45 +524,94 @@ __global__ __launch_bounds__(256) void mse_grad(const float* __restrict__ o, con
 
 // One full pass B = Bx By Bz of the binomial low-pass on a 32 x 8 x 8 output tile staged with a
 // one-voxel halo in LDS (the three separable passes share the tile).
-constexpr int SMX = 32, SMY = 8, SMZ = 8;
-__global__ __launch_bounds__(256) void smooth3(const float* __restrict__ src, float* __restrict__ dst, Grid3 g) {
-  __shared__ float t0[SMZ + 2][SMY + 2][SMX + 2];
-  __shared__ float t1[SMZ + 2][SMY + 2][SMX];
-  __shared__ float t2[SMZ + 2][SMY][SMX];
-  const int tid = threadIdx.x;
+// One pass of the separable binomial low-pass [1/4, 1/2, 1/4] along x, then y, then z (zero
+// fill outside a Dirichlet box, wrap-around on a periodic one).  A workgroup owns a 64 x 16
+// column of outputs and marches through a chunk of z-planes: each input plane is staged with its
+// one-point x and y halo in a double-buffered LDS tile (the next plane is fetched into registers
+// while the current one is filtered), the x- and y-passes run from LDS, and the z-pass keeps the
+// xy-filtered values of the two previous planes in registers.
+constexpr int SMX = 64, SMY = 16, SMR = SMY + 2, SMROWS = (SMR + 3) / 4;
+
+__global__ __launch_bounds__(256) void smooth3(const float* __restrict__ src, float* __restrict__ dst, Grid3 g,
+                                               int zc) {
+  __shared__ float t[2][SMR][SMX + 2];
+  const int tid = threadIdx.x, lx = tid & 63, ly = tid >> 6;
   const int tx = (g.nx + SMX - 1) / SMX, ty = (g.ny + SMY - 1) / SMY;
-  const int b = blockIdx.x;
-  const int x0 = (b % tx) * SMX, y0 = ((b / tx) % ty) * SMY, z0 = (b / (tx * ty)) * SMZ;
+  int b = blockIdx.x;
+  const int x0 = (b % tx) * SMX;
+  b /= tx;
+  const int y0 = (b % ty) * SMY;
+  const int z0 = (b / ty) * zc;
+  const int z1 = min(z0 + zc, g.nz);
+  const int nplanes = z1 - z0 + 2;  // the chunk plus one halo plane on each side
   const int64_t plane = (int64_t)g.nx * g.ny;
-  for (int v = tid; v < (SMZ + 2) * (SMY + 2) * (SMX + 2); v += 256) {
-    const int sx = v % (SMX + 2), sy = (v / (SMX + 2)) % (SMY + 2), sz = v / ((SMX + 2) * (SMY + 2));
-    int gx = x0 + sx - 1, gy = y0 + sy - 1, gz = z0 + sz - 1;
-    bool ok = true;
-    if (g.periodic) {
-      gx = (gx + g.nx) % g.nx; gy = (gy + g.ny) % g.ny; gz = (gz + g.nz) % g.nz;
-    } else {
-      ok = gx >= 0 && gx < g.nx && gy >= 0 && gy < g.ny && gz >= 0 && gz < g.nz;
+  // wrapped (periodic) or range-checked (Dirichlet) index along one axis; -1 = outside
+  auto fold = [&](int i, int n) -> int {
+    if (g.periodic) return ((i % n) + n) % n;
+    return (i >= 0 && i < n) ? i : -1;
+  };
+  // staged points this thread loads: its column x0 + lx on rows ly, ly + 4, ... of the tile, and
+  // for the first 2 SMR threads one halo column point (left for tid < SMR, right otherwise)
+  const int cx = fold(x0 + lx, g.nx);
+  int64_t rowoff[SMROWS];
+#pragma unroll
+  for (int i = 0; i < SMROWS; ++i) {
+    const int r = ly + 4 * i;
+    const int gy = r < SMR ? fold(y0 + r - 1, g.ny) : -1;
+    rowoff[i] = (gy < 0 || cx < 0) ? -1 : (int64_t)gy * g.nx + cx;
+  }
+  const bool halo = tid < 2 * SMR;
+  const int hr = tid % SMR, hc = tid < SMR ? 0 : SMX + 1;
+  int64_t hoff = -1;
+  if (halo) {
+    const int gy = fold(y0 + hr - 1, g.ny), gx = fold(x0 + (hc == 0 ? -1 : SMX), g.nx);
+    hoff = (gy < 0 || gx < 0) ? -1 : (int64_t)gy * g.nx + gx;
+  }
+  float pm[SMROWS], ph = 0.f;
+  auto fetch = [&](int k) {
+    const int gz = fold(z0 - 1 + k, g.nz);
+    const float* sp = src + (int64_t)(gz < 0 ? 0 : gz) * plane;
+#pragma unroll
+    for (int i = 0; i < SMROWS; ++i) pm[i] = (gz >= 0 && rowoff[i] >= 0) ? sp[rowoff[i]] : 0.f;
+    if (halo) ph = (gz >= 0 && hoff >= 0) ? sp[hoff] : 0.f;
+  };
+  auto stash = [&](int buf) {
+#pragma unroll
+    for (int i = 0; i < SMROWS; ++i)
+      if (ly + 4 * i < SMR) t[buf][ly + 4 * i][lx + 1] = pm[i];
+    if (halo) t[buf][hr][hc] = ph;
+  };
+  // output rows 4 ly .. 4 ly + 3 of the column; their xy-filtered values on the two previous planes
+  float s0[4] = {0.f, 0.f, 0.f, 0.f}, s1[4] = {0.f, 0.f, 0.f, 0.f};
+  const int gxo = x0 + lx;
+  fetch(0);
+  for (int k = 0; k < nplanes; ++k) {
+    const int buf = k & 1;
+    stash(buf);
+    if (k + 1 < nplanes) fetch(k + 1);
+    __syncthreads();
+    float xr[6];
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      const float* row = &t[buf][4 * ly + i][lx];
+      xr[i] = 0.25f * row[0] + 0.5f * row[1] + 0.25f * row[2];
     }
-    t0[sz][sy][sx] = ok ? src[(int64_t)gz * plane + (int64_t)gy * g.nx + gx] : 0.f;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const float s2 = 0.25f * xr[j] + 0.5f * xr[j + 1] + 0.25f * xr[j + 2];
+      const int gy = y0 + 4 * ly + j;
+      if (k >= 2 && gxo < g.nx && gy < g.ny)
+        dst[(int64_t)(z0 + k - 2) * plane + (int64_t)gy * g.nx + gxo] = 0.25f * s0[j] + 0.5f * s1[j] + 0.25f * s2;
+      s0[j] = s1[j];
+      s1[j] = s2;
+    }
   }
-  __syncthreads();
-  for (int v = tid; v < (SMZ + 2) * (SMY + 2) * SMX; v += 256) {
-    const int x = v % SMX, y = (v / SMX) % (SMY + 2), z = v / (SMX * (SMY + 2));
-    t1[z][y][x] = 0.25f * t0[z][y][x] + 0.5f * t0[z][y][x + 1] + 0.25f * t0[z][y][x + 2];
-  }
-  __syncthreads();
-  for (int v = tid; v < (SMZ + 2) * SMY * SMX; v += 256) {
-    const int x = v % SMX, y = (v / SMX) % SMY, z = v / (SMX * SMY);
-    t2[z][y][x] = 0.25f * t1[z][y][x] + 0.5f * t1[z][y + 1][x] + 0.25f * t1[z][y + 2][x];
-  }
-  __syncthreads();
-  for (int v = tid; v < SMZ * SMY * SMX; v += 256) {
-    const int x = v % SMX, y = (v / SMX) % SMY, z = v / (SMX * SMY);
-    const int gx = x0 + x, gy = y0 + y, gz = z0 + z;
-    if (gx < g.nx && gy < g.ny && gz < g.nz)
-      dst[(int64_t)gz * plane + (int64_t)gy * g.nx + gx] =
-          0.25f * t2[z][y][x] + 0.5f * t2[z + 1][y][x] + 0.25f * t2[z + 2][y][x];
-  }
+}
+
+// z-planes per workgroup of the low-pass: enough workgroups to fill the chip several times over
+static int smooth_zchunk(Grid3 g) {
+  const int64_t cols = (int64_t)((g.nx + SMX - 1) / SMX) * ((g.ny + SMY - 1) / SMY);
+  return (int)std::max<int64_t>(8, std::min<int64_t>(64, (int64_t)g.nz * cols / 8192));
 }
 
 __global__ __launch_bounds__(256) void f32_to_bf16_kernel(const float* __restrict__ src, uint16_t* __restrict__ dst,
@@ -852,13 +901,12 @@ static int forward_layers(tbs_net* n, Grid3 g, int keep) {
 // buf <- B^SMOOTH_PASSES buf with B = Bx By Bz the binomial low-pass; tmp is scratch of N floats
 static int smooth(tbs_net* n, float* buf, float* tmp, Grid3 g) {
   const int64_t N = (int64_t)g.nx * g.ny * g.nz;
-  int blocks = (int)std::min<int64_t>((N + 255) / 256, 8192);
-  (void)blocks;
-  const int sblocks = ((g.nx + SMX - 1) / SMX) * ((g.ny + SMY - 1) / SMY) * ((g.nz + SMZ - 1) / SMZ);
+  const int zc = smooth_zchunk(g);
+  const int sblocks = ((g.nx + SMX - 1) / SMX) * ((g.ny + SMY - 1) / SMY) * ((g.nz + zc - 1) / zc);
   float* a = buf;
   float* b = tmp;
   for (int p = 0; p < SMOOTH_PASSES; ++p) {
-    hipLaunchKernelGGL(smooth3, dim3(sblocks), dim3(256), 0, n->st, (const float*)a, b, g);
+    hipLaunchKernelGGL(smooth3, dim3(sblocks), dim3(256), 0, n->st, (const float*)a, b, g, zc);
     float* t = a; a = b; b = t;
   }
   if (a != buf) NCHK(hipMemcpyAsync(buf, a, (size_t)N * 4, hipMemcpyDeviceToDevice, n->st));
