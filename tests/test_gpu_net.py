@@ -95,8 +95,9 @@ def _x0(u, q):
 
 
 @pytest.mark.parametrize("circular", [False, True])
-def test_forward_end_to_end(circular):
-    grid, tau = (24, 20, 17), 1e-3
+@pytest.mark.parametrize("grid", [(24, 20, 17), (70, 20, 17)])   # one and two 64-wide low-pass tiles
+def test_forward_end_to_end(circular, grid):
+    tau = 1e-3
     theta = cnn_init(11)
     theta[-1] = 0.1
     net = _net(grid, theta=theta)
