@@ -763,9 +763,16 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     st.skipped_learned_guess = 1;
   }
 
-  // initial guess: plain u^k, or the network guess if its FP64 residual is smaller
-  rc = copy_async(c, u_next, u_prev, N * 8);
-  if (rc) return rc;
+  // initial guess: plain u^k, or the network guess if its FP64 residual is smaller.  The current
+  // iterate is u_next once have_x is set, else u_prev itself: u_next is only written when a guess
+  // is formed there, when a path needs it in place, or by the first refinement correction
+  // (u_next = u_prev + d), which saves a full FP64 copy per step.
+  bool have_x = false;
+  auto ensure_x = [&]() -> int {
+    if (have_x) return TBS_OK;
+    have_x = true;
+    return copy_async(c, u_next, u_prev, N * 8);
+  };
   // refined path: the plain guess's residual (FP32 copy, norms and partial sums) is the first
   // refinement sweep's residual whenever the plain guess is kept, so it is computed last and reused
   bool have_res0 = false;
@@ -776,6 +783,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     rc = tbs_net_guess_internal(g, grid, c->bc == TBS_BC_PERIODIC, c->tau, c->st, u_prev, q, &du);
     if (rc) return rc;
     HIPCHK(launch_guess_combine(u_next, u_prev, du, c->N, c->st));
+    have_x = true;
     rc = fp64_relres(c, u_next, b64, &st.rel_res_learned);
     if (rc) return rc;
     if (prec == TBS_PREC_MIXED || prec == TBS_PREC_MIXED_BF16) {
@@ -792,8 +800,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
       st.used_learned_guess = 1;
       c->guess_rejects = 0;
     } else {
-      rc = copy_async(c, u_next, u_prev, N * 8);
-      if (rc) return rc;
+      have_x = false;  // back to the plain guess u_prev
       have_res0 = (prec == TBS_PREC_MIXED || prec == TBS_PREC_MIXED_BF16);
       ++c->guess_rejects;
       if (c->opts.guess_backoff) c->guess_wait = 1 << std::min(c->guess_rejects - 1, 6);
@@ -834,6 +841,8 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     rc = cg_loop(cc, Ac, 0, 0, c->opts.inner_max_iter, &cit);
     if (rc < 0 && rc != TBS_E_BREAKDOWN) return rc;
     st.coarse_iters = cit;
+    rc = ensure_x();  // the last prolongation pass adds into u_next = u_prev
+    if (rc) return rc;
     {  // prolongation, added to u_next = u_prev
       const int d1[3] = {cx, cy, nz}, d2[3] = {cx, ny, nz}, d3[3] = {nx, ny, nz};
       HIPCHK(launch_transfer(xc, t2, d1, cz, 2, 1, per, c->n, 1.0, 0, c->st));
@@ -859,14 +868,15 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     if (st.rel_res_coarse < st.rel_res_plain) {
       st.used_coarse_guess = 1;
     } else {
-      rc = copy_async(c, u_next, u_prev, N * 8);
-      if (rc) return rc;
+      have_x = false;  // back to the plain guess u_prev
       have_res0 = false;
     }
   }
 
   int result = TBS_OK;
   if (prec == TBS_PREC_FP64) {
+    rc = ensure_x();  // CG iterates in place on u_next
+    if (rc) return rc;
     CgArrays A{u_next, c->ws + L.off[1], {c->ws + L.off[2], c->ws + L.off[3]}, c->ws + L.off[4], nullptr, nullptr};
     rc = cg_init_async(c, b64, A, 0, rtol);
     if (rc) return rc;
@@ -921,7 +931,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
       if (sweeps == 0 && have_res0) {
         s = res0;  // r32 and the residual partial sums of u_next = u_prev are already in place
       } else {
-        rc = resid_async(c, u_next, b64, r32, TBS_F32, SC_AUX, FIN_NORMS, 0.0);
+        rc = resid_async(c, have_x ? u_next : u_prev, b64, r32, TBS_F32, SC_AUX, FIN_NORMS, 0.0);
         if (rc) return rc;
         rc = read_scal(c, SC_AUX, &s);
         if (rc) return rc;
@@ -947,9 +957,16 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
       total += nit;
       if (irc == TBS_E_BREAKDOWN && nit == 0) { result = irc; break; }
       if (irc < 0 && irc != TBS_E_BREAKDOWN) return irc;
-      HIPCHK(launch_add_f32_to_f64(u_next, d32, c->N, c->st));
+      if (have_x) {
+        HIPCHK(launch_add_f32_to_f64(u_next, d32, c->N, c->st));
+      } else {
+        HIPCHK(launch_guess_combine(u_next, u_prev, d32, c->N, c->st));  // u_next = u_prev + d
+        have_x = true;
+      }
       ++sweeps;
     }
+    rc = ensure_x();  // no correction was added: the answer is the guess u_prev
+    if (rc) return rc;
     st.iters = total;
     st.sweeps = sweeps;
   }

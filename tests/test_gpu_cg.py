@@ -237,3 +237,28 @@ def test_timestep_bitwise_reproducible_and_resumable():
     resumed = host(run(dev(ckpt), 2))
     assert np.array_equal(straight, resumed)
     assert np.array_equal(straight, host(run(u0, 4)))
+
+
+@pytest.mark.parametrize("prec", [tbs.PREC_FP64, tbs.PREC_MIXED, tbs.PREC_MIXED_BF16])
+@pytest.mark.parametrize("coarse", [0, 1])
+def test_timestep_output_independent_of_prior_contents(prec, coarse):
+    # u_next is output only: the step writes every entry whatever it held before (the refined
+    # path forms u_next = u_prev + d on its first correction instead of copying u_prev first)
+    grid, n, tau = (40, 26, 18), 3, 2e-3
+    h = tuple(1.0 / (N + 1) for N in grid)
+    u = dev(normal_field(grid[::-1], 21))
+    ctx = tbs.Context(grid, n, h, tau, "dirichlet")
+    ctx.set_opts(coarse_guess=coarse)
+    ctx.ensure_workspace(prec)
+    a = dev(np.zeros(grid[::-1]))
+    b = dev(np.full(grid[::-1], np.nan))
+    sa = ctx.timestep(u, None, a, prec, 1e-8, 2000)
+    sb = ctx.timestep(u, None, b, prec, 1e-8, 2000)
+    assert sa["converged"] and sb["converged"]
+    assert np.array_equal(host(a), host(b))
+    # a step that needs no correction returns its initial guess: u_prev itself, or the coarse guess
+    c = dev(np.full(grid[::-1], np.nan))
+    sc = ctx.timestep(u, None, c, prec, 10.0, 2000)
+    assert sc["iters"] == 0 and np.all(np.isfinite(host(c)))
+    if not sc["used_coarse_guess"]:
+        assert np.array_equal(host(c), host(u))
