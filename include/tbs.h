@@ -177,7 +177,9 @@ int tbs_cg_step(tbs_ctx* ctx, int n_iters, double* rel_res_out, int* iters_out);
  * u_prev, q (nullable), u_next: FP64 device arrays.  prec selects the arithmetic (tbs_prec).
  * net: optional learned initial guess; its guess is kept only if its FP64 residual is smaller
  * than that of the plain guess u_prev (tbs_opts.guess_backoff: whether a rejected network is
- * skipped on the following steps).  Synchronises; fills *stats if not NULL. */
+ * skipped on the following steps).  u_next is output only (its prior contents are never read);
+ * it holds the answer on TBS_OK, TBS_W_NOT_CONVERGED and TBS_E_BREAKDOWN and is unspecified
+ * after any other error.  Synchronises; fills *stats if not NULL. */
 int tbs_timestep(tbs_ctx* ctx, const double* u_prev, const double* q, double* u_next, int prec,
                  double rtol, int max_iter, tbs_net* net, tbs_stats* stats);
 
