@@ -107,8 +107,11 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     e0.record(stream)
+    step_ms = []
     for i in range(args.steps):
-        stats.append(step(tbs.PREC_MIXED, net is not None))
+        ts = time.perf_counter()
+        stats.append(step(tbs.PREC_MIXED, net is not None))  # synchronises
+        step_ms.append((time.perf_counter() - ts) * 1e3)
         log("step %d: iters %d sweeps %d rel_res %.3e learned %d" % (
             i, stats[-1]["iters"], stats[-1]["sweeps"], stats[-1]["rel_res_fp64"], stats[-1]["used_learned_guess"]))
     e1.record(stream)
@@ -137,6 +140,8 @@ def main():
                    "rtol": w.rtol, "solver": "fp64-refined fp32 CG" + (" + learned guess" if net else ""),
                    "global_batch": 1, "parallelism": "none"},
         "wall_s_timed": round(wall, 3),
+        "step_ms_host": {"median": round(float(np.median(step_ms)), 3), "min": round(min(step_ms), 3),
+                         "max": round(max(step_ms), 3), "first": round(step_ms[0], 3), "last": round(step_ms[-1], 3)},
         "iters_per_step": [s["iters"] for s in stats], "sweeps_per_step": [s["sweeps"] for s in stats],
         "learned_guess_used": [s["used_learned_guess"] for s in stats],
         "learned_over_plain_residual": [round(s["rel_res_learned"] / s["rel_res_plain"], 4)
@@ -240,6 +245,8 @@ def probe(args):
 
 def extras(ctx, tbs, torch, w, u0, stream, net, N, k_all):
     """Apply throughput per dtype and seconds per step of the other solver variants."""
+    import numpy as np
+
     res = {}
     with torch.cuda.stream(stream):
         y64 = torch.empty_like(u0)
@@ -249,18 +256,24 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N, k_all):
     torch.cuda.synchronize()
     gd = {}
     for name, u, y in (("f64", u0, y64), ("f32", u32, y32), ("bf16_to_f32", u16, y32)):
-        for _ in range(2):
+        for _ in range(5):
             ctx.apply(u, y)
         torch.cuda.synchronize()
         ctx.prof_enable(True)
-        reps = 10
-        for _ in range(reps):
+        reps = 20
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record(stream)
             ctx.apply(u, y)
+            b.record(stream)
+        torch.cuda.synchronize()
         p = ctx.prof_read()
         ctx.prof_enable(False)
         ms, by, cnt = list(p.values())[0]
+        med = float(np.median([a.elapsed_time(b) for a, b in ev]))
         gd[name] = {"GDoF/s": round(N / (ms / cnt / 1e3) / 1e9, 1), "GB/s": round(by / (ms / 1e3) / 1e9, 1),
-                    "frac_hbm": round(by / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "ms": round(ms / cnt, 4)}
+                    "frac_hbm": round(by / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "ms": round(ms / cnt, 4),
+                    "ms_median_of_%d" % reps: round(med, 4), "GDoF/s_median": round(N / (med / 1e3) / 1e9, 1)}
         log("apply %s: %s" % (name, gd[name]))
     # practical ceiling: a plain device-to-device copy of the FP32 field (read 4 B + write 4 B per DoF)
     with torch.cuda.stream(stream):
