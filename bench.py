@@ -160,14 +160,27 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-# the sources of the stencil kernels: a traffic summary holds only while they hash as measured
+# the sources of the stencil kernels and of their launch geometry (the host's tile / z-chunk plan):
+# a traffic summary holds only while they hash as measured
 STENCIL_SOURCES = ("stencil_kernel.h", "stencil.hip", "stencil.h", "common.h")
+
+
+def stencil_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1904_03057_amd", "csrc")
+    for f in STENCIL_SOURCES:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
+    api = open(os.path.join(csrc, "api.cpp")).read()
+    start = api.index("static void plan_geometry(")
+    h.update(api[start:api.index("\n}\n", start) + 3].encode())
+    return h.hexdigest()
 
 
 def measured_traffic(kernel):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter summary, or None when
     there is none for it or the stencil sources have changed since the counters were taken."""
-    import hashlib
     path = os.path.join(ROOT, "profiles", "%s_heat928_traffic.txt" % kernel)
     if not os.path.exists(path):
         return None
@@ -176,11 +189,7 @@ def measured_traffic(kernel):
         if "=" in line and not line.startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    h = hashlib.sha256()
-    for f in STENCIL_SOURCES:
-        with open(os.path.join(ROOT, "paper_1904_03057_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
-    if kv.get("kernel") != kernel or kv.get("source_sha256") != h.hexdigest():
+    if kv.get("kernel") != kernel or kv.get("source_sha256") != stencil_sources_hash():
         return None
     return int(float(kv["traffic_bytes_per_launch"]))
 

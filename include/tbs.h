@@ -82,9 +82,12 @@ typedef struct {
   int inner_max_iter;      /* refinement: inner iteration cap per sweep (default 500) */
   int max_sweeps;          /* refinement: sweep cap (default 12) */
   int poll_every;          /* CG iterations enqueued between host convergence polls (default 4) */
-  int zchunk;              /* z-planes per workgroup of the stencil kernels (0 = automatic); results
-                              do not depend on it (each output sums its terms in the same order) */
-  int tile_order;          /* stencil tile order: 0 x-tiles fastest, 1 y-tiles fastest (no effect on results) */
+  int zchunk;              /* z-planes per workgroup of the stencil kernels (0 = automatic); operator
+                              outputs do not depend on it (each output sums its terms in the same
+                              order); dot products group their terms by workgroup, so it changes
+                              them, and the CG iterates, at rounding level */
+  int tile_order;          /* stencil tile order: 0 x-tiles fastest (default), 1 y-tiles fastest
+                              (same effect on results as zchunk) */
   int nt_store;            /* 1: stencil outputs use non-temporal stores (no effect on results) */
   int fused_cg;            /* FP32 inner CG (TBS_PREC_FP32, MIXED, MIXED_BF16, tbs_cg_step in F32):
                               1 = one kernel per iteration (default): r and p formed while staging,

@@ -121,8 +121,10 @@ static void plan_geometry(tbs_ctx* c, int zchunk) {
   c->tiles_y = (int)((c->ny + kTileY - 1) / kTileY);  // finest tiling: bounds the partial-sum count
   const int64_t tiles = (int64_t)c->tiles_x * c->tiles_y;
   const int64_t plan_tiles = (int64_t)c->tiles_x * ((c->ny + kTileYPlan - 1) / kTileYPlan);
-  // enough blocks to fill 256 CUs several times, but chunks of at least 4(2n+1) planes
-  int64_t want = (4096 + plan_tiles - 1) / plan_tiles;
+  // about 8192 workgroups (many times what 256 CUs hold at once: the z-marching waves finish at
+  // different times and short chunks even out the tail), but chunks of at least 4(2n+1) planes;
+  // at 928^3 this gives 93-plane chunks, 1 % faster for the CG iteration than 186
+  int64_t want = (8192 + plan_tiles - 1) / plan_tiles;
   const int64_t minzc = std::max<int64_t>(16, 4 * (2 * c->n + 1));
   int64_t maxchunks = std::max<int64_t>(1, c->nz / minzc);
   int64_t chunks = std::min(want, maxchunks);
