@@ -16,6 +16,7 @@
 #include "net.h"
 #include "stencil.h"
 #include "transfer.h"
+#include "refine.h"
 
 using namespace tbs;
 
@@ -582,9 +583,10 @@ static int cgf_async(tbs_ctx* c, const CgArrays& A, int dt, int k) {
   return TBS_OK;
 }
 
-// Runs CG iterations k = k0 .. until done / max_iter, then flushes the pending x update.
+// Runs CG iterations k = k0 .. until done / max_iter, then flushes the pending x update (unless
+// keep_pending: the caller then applies it, e.g. with launch_refine_add, and clears the flag).
 // Returns TBS_OK, TBS_W_NOT_CONVERGED or TBS_E_BREAKDOWN; *nit receives the completed count.
-static int cg_loop(tbs_ctx* c, const CgArrays& A, int dt, int k0, int max_iter, int* nit) {
+static int cg_loop(tbs_ctx* c, const CgArrays& A, int dt, int k0, int max_iter, int* nit, bool keep_pending = false) {
   int k = k0, rc;
   Scalars s;
   rc = read_scal(c, SC_CG, &s);
@@ -600,8 +602,10 @@ static int cg_loop(tbs_ctx* c, const CgArrays& A, int dt, int k0, int max_iter, 
     k = s.nit;
     prof_collect(c, s.nit);
   }
-  HIPCHK(launch_flush(A.x, A.p[0], A.p[1], c->N, dt, scal(c, SC_CG), c->st));
-  HIPCHK(launch_finalize(FIN_CLEAR_PENDING, nullptr, nullptr, 0, scal(c, SC_CG), 0.0, c->st));
+  if (!keep_pending) {
+    HIPCHK(launch_flush(A.x, A.p[0], A.p[1], c->N, dt, scal(c, SC_CG), c->st));
+    HIPCHK(launch_finalize(FIN_CLEAR_PENDING, nullptr, nullptr, 0, scal(c, SC_CG), 0.0, c->st));
+  }
   *nit = s.nit;
   if (s.status == TBS_E_BREAKDOWN) return set_err(TBS_E_BREAKDOWN, "CG breakdown after %d iterations", s.nit);
   return s.done ? TBS_OK : TBS_W_NOT_CONVERGED;
@@ -955,16 +959,16 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
                              eta, c->st));
       int nit = 0;
       const int cap = std::min(c->opts.inner_max_iter, std::max(1, max_iter - total));
-      int irc = cg_loop(c, A, dt, 0, cap, &nit);
+      // the inner solve's last x update is left pending and applied by the refinement update:
+      // u_next = (u_next or u_prev) + (d + alpha p) in one pass over the arrays
+      int irc = cg_loop(c, A, dt, 0, cap, &nit, true);
       total += nit;
       if (irc == TBS_E_BREAKDOWN && nit == 0) { result = irc; break; }
       if (irc < 0 && irc != TBS_E_BREAKDOWN) return irc;
-      if (have_x) {
-        HIPCHK(launch_add_f32_to_f64(u_next, d32, c->N, c->st));
-      } else {
-        HIPCHK(launch_guess_combine(u_next, u_prev, d32, c->N, c->st));  // u_next = u_prev + d
-        have_x = true;
-      }
+      HIPCHK(launch_refine_add(u_next, have_x ? u_next : u_prev, d32, A.p[0], A.p[1], c->N, dt, scal(c, SC_CG),
+                               c->st));
+      HIPCHK(launch_finalize(FIN_CLEAR_PENDING, nullptr, nullptr, 0, scal(c, SC_CG), 0.0, c->st));
+      have_x = true;
       ++sweeps;
     }
     rc = ensure_x();  // no correction was added: the answer is the guess u_prev

@@ -6,6 +6,7 @@
 // fixed order.  No floating-point atomics are used, so results are bitwise reproducible.
 #include "common.h"
 #include "stencil.h"
+#include "refine.h"
 
 namespace tbs {
 
@@ -102,6 +103,22 @@ __global__ __launch_bounds__(256) void flush_kernel(T* __restrict__ x, const Tp*
   const int64_t stride = (int64_t)gridDim.x * 256;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
     x[i] += alpha * Io<Tp>::template ld<T>(p, i);
+}
+
+// out = base + (d + alpha p), the FP32 part formed exactly as flush_kernel forms x + alpha p
+template <typename Tp>
+__global__ __launch_bounds__(256) void refine_add_kernel(double* out, const double* base, const float* __restrict__ d,
+                                                         const Tp* __restrict__ p0, const Tp* __restrict__ p1,
+                                                         int64_t n, const Scalars* s) {
+  const bool pending = s->pending != 0;
+  const float alpha = (float)s->alpha;
+  const Tp* p = (s->nit & 1) ? p1 : p0;
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    float x = d[i];
+    if (pending) x += alpha * Io<Tp>::template ld<float>(p, i);
+    out[i] = base[i] + (double)x;
+  }
 }
 
 template <typename T>
@@ -267,6 +284,18 @@ hipError_t launch_flush(void* x, const void* p0, const void* p1, int64_t n, int 
                        (const float*)p1, n, s);
   else
     hipLaunchKernelGGL((flush_kernel<float, uint16_t>), dim3(b), dim3(256), 0, st, (float*)x, (const uint16_t*)p0,
+                       (const uint16_t*)p1, n, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_refine_add(double* out, const double* base, const float* d, const void* p0, const void* p1,
+                             int64_t n, int dt, const Scalars* s, hipStream_t st) {
+  const int b = vec_blocks(n);
+  if (dt == 1)
+    hipLaunchKernelGGL(refine_add_kernel<float>, dim3(b), dim3(256), 0, st, out, base, d, (const float*)p0,
+                       (const float*)p1, n, s);
+  else
+    hipLaunchKernelGGL(refine_add_kernel<uint16_t>, dim3(b), dim3(256), 0, st, out, base, d, (const uint16_t*)p0,
                        (const uint16_t*)p1, n, s);
   return hipGetLastError();
 }
