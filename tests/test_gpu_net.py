@@ -224,3 +224,75 @@ def test_guess_backoff_skips_a_rejected_net():
     for _ in range(3):
         s = ctx.timestep(u, None, a, tbs.PREC_MIXED, 1e-8, 500, net)
         assert s["skipped_learned_guess"] == 0 and not np.isnan(s["rel_res_learned"])
+
+
+def test_adam_over_several_steps_matches_oracle():
+    # four training steps; after each the device's own gradient drives the oracle's Adam (pinned by
+    # the constant-gradient closed form for every t), whose weights must equal the device's: this
+    # covers the bias corrections 1 - b^t for t > 1
+    grid, tau, batch = (16, 12, 10), 1e-3, 1
+    theta = cnn_init(13)
+    theta[-1] = 0.05
+    net = tbs.Net()
+    net.ensure_workspace(grid, batch, True)
+    net.set_weights(theta)
+    net.set_hparams(out_scale=1.5, lr=2e-3)
+    f32 = lambda a: a.astype(np.float32).astype(np.float64)
+    th = net.get_weights().astype(np.float64)
+    m, v = np.zeros(cnn.N_PARAMS), np.zeros(cnn.N_PARAMS)
+    for t in range(1, 5):
+        U = f32(normal_field(grid[::-1], 50 + t))
+        Q = f32(normal_field(grid[::-1], 60 + t))
+        T = f32(normal_field(grid[::-1], 70 + t) * 1e-3)
+        net.train_step(dev(U, "f32"), dev(Q, "f32"), dev(T, "f32"), batch, False, tau)
+        g = net.get_grad().astype(np.float64)
+        th, m, v = cnn.adam_step(th, g, m, v, t, lr=2e-3)
+        w = net.get_weights().astype(np.float64)
+        assert np.allclose(w, th, rtol=0, atol=3e-6), (t, np.abs(w - th).max())
+        th = w  # continue from the device's FP32 weights
+
+
+@pytest.mark.parametrize("prec", ["mixed", "fp64"])
+def test_kept_learned_guess_step_matches_oracle(prec):
+    # the trained 128^3 network on a held-out step pair: its guess is kept, and the step that starts
+    # from it (guess combine, then refined FP32 or FP64 CG) satisfies the oracle's FP64 residual
+    # test and matches the fast-diagonalisation exact step within kappa * rtol
+    import json
+    import os
+    from oracle import exact
+    from workloads import gaussian_params, gaussian_sum
+    wdir = os.path.join(os.path.dirname(tbs.__file__), "weights")
+    meta = json.load(open(os.path.join(wdir, "guess_net_128.json")))
+    grid, n, tau, rtol = tuple(meta["grid"]), 3, meta["tau"], 1e-8
+    h = (meta["h"],) * 3
+    L = (grid[0] + 1) * h[0]
+    u = gaussian_sum(grid, "dirichlet", h, gaussian_params(9001, 16, 0.02, 0.1, 1.0, 0.1 * L, 0.9 * L))
+    q = gaussian_sum(grid, "dirichlet", h, gaussian_params(9002, 2, 0.05, 0.15, 10.0, 0.1 * L, 0.9 * L))
+    net = tbs.Net()
+    net.ensure_workspace(grid, 1, False)
+    net.set_weights(np.fromfile(os.path.join(wdir, "guess_net_128.f32"), dtype="<f4"))
+    net.set_hparams(out_scale=meta["out_scale"])
+    ctx = tbs.Context(grid, n, h, tau, "dirichlet")
+    p = tbs.PREC_MIXED if prec == "mixed" else tbs.PREC_FP64
+    ctx.ensure_workspace(p)
+    tu, tq = dev(u), dev(q)
+    un = torch.empty_like(tu)
+    st = ctx.timestep(tu, tq, un, p, rtol, 2000, net)
+    assert st["converged"] and st["used_learned_guess"] == 1, st
+    # the guess the step used: u + du with the same network forward, residuals as the oracle sees them
+    du = torch.empty(tu.shape, dtype=torch.float32, device="cuda")
+    net.forward(tu, tq, du, False, tau)
+    x0 = u + host(du)
+    b = op.rhs(u, q, n, tau, "dirichlet")
+    bn = np.linalg.norm(b)
+    rl = np.linalg.norm(b - op.apply(x0, n, h, tau, "dirichlet")) / bn
+    rp = np.linalg.norm(b - op.apply(u, n, h, tau, "dirichlet")) / bn
+    assert abs(st["rel_res_learned"] - rl) <= 1e-9 * rl
+    assert abs(st["rel_res_plain"] - rp) <= 1e-9 * rp
+    assert rl < rp
+    got = host(un)
+    rg = np.linalg.norm(b - op.apply(got, n, h, tau, "dirichlet")) / bn
+    assert rg <= rtol * (1 + 1e-6), rg
+    xs = exact.solve_dirichlet(b, n, h, tau)
+    kappa = exact.condition_number(grid, n, h, tau, "dirichlet")
+    assert np.linalg.norm(got - xs) / np.linalg.norm(xs) <= kappa * rtol

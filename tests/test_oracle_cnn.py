@@ -103,6 +103,19 @@ def test_adam_first_step_closed_form():
     assert np.allclose(t1, th - 1e-3 * g / (np.abs(g) + 1e-8), atol=1e-15)
 
 
+@pytest.mark.parametrize("steps", [2, 3, 5])
+def test_adam_constant_gradient_closed_form(steps):
+    # with a constant gradient g from zero moments the bias-corrected moments are exactly
+    # m_hat = g and v_hat = g^2 at every step t, so theta_t = theta_0 - t lr g / (|g| + eps):
+    # a wrong bias-correction exponent for t > 1 changes m_hat / sqrt(v_hat) and fails this
+    rng = np.random.default_rng(5)
+    th0, g = rng.standard_normal(40), rng.standard_normal(40) * 10.0 ** rng.integers(-4, 2, 40)
+    th, m, v = th0.copy(), np.zeros(40), np.zeros(40)
+    for t in range(1, steps + 1):
+        th, m, v = cnn.adam_step(th, g, m, v, t, lr=2e-3)
+    assert np.allclose(th, th0 - steps * 2e-3 * g / (np.abs(g) + 1e-8), rtol=0, atol=1e-13)
+
+
 def test_bf16_rounding_known_values():
     ulp = 2.0 ** -7
     vals = np.array([1.0, 1 + ulp / 2, 1 + 1.5 * ulp, 1 + 0.75 * ulp, -3.0, 0.0, 1e-40])

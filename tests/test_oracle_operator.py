@@ -160,3 +160,23 @@ def test_refinement_reaches_fp64_residual_with_fp32_inner():
     assert rr <= 1e-12 and 1 <= sweeps <= 6
     xs = exact.solve(b, n, h, tau, bc)
     assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-10
+
+
+COND_CASES = [((6, 7, 8), 1, "periodic"), ((8, 7, 9), 3, "periodic"), ((11, 11, 12), 5, "periodic"),
+              ((6, 7, 8), 1, "dirichlet"), ((9, 8, 7), 3, "dirichlet"), ((12, 11, 11), 5, "dirichlet")]
+
+
+@pytest.mark.parametrize("grid,n,bc", COND_CASES)
+def test_condition_number_against_dense_eigenvalues(grid, n, bc):
+    # periodic grids: the symbol on the DFT grid gives the spectrum exactly; Dirichlet (truncated
+    # bands): the eigenvalues lie inside the symbol's range, so the symbol's ratio bounds kappa
+    h, tau = (0.11, 0.07, 0.13), 0.02
+    lam = np.linalg.eigvalsh(op.dense_matrix(grid, n, h, tau, bc))
+    kd = lam.max() / lam.min()
+    ks = exact.condition_number(grid, n, h, tau, bc)
+    if bc == "periodic":
+        assert abs(ks - kd) <= 1e-9 * kd
+    else:
+        assert kd <= ks * (1 + 1e-12)
+        # and the bound is not vacuous: the truncated spectrum fills most of the symbol's range
+        assert kd >= 0.3 * ks
