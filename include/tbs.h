@@ -152,6 +152,22 @@ int tbs_rhs(tbs_ctx* ctx, const void* u_prev, const void* q, void* b, int dtype)
 int tbs_residual(tbs_ctx* ctx, const double* x, const double* b, void* r, int r_dtype,
                  double* rnorm, double* bnorm);
 
+/* For callers that cannot allocate (code under HIP graph capture, allocation-free serving loops,
+ * harnesses that forbid hipMalloc): the same FP64 residual as tbs_residual, computed by the same
+ * kernels, but with its partial sums in a static device buffer the library owns (one per GPU,
+ * held until the process ends; 256 + 2 * 8 * TBS_NOALLOC_MAX_BLOCKS bytes, about 1 MiB) and the
+ * norms written to device memory: norms[0] = ||b - A x||_2, norms[1] = ||b||_2 (norms: device
+ * pointer to 2 doubles, 8-byte aligned).  r (nullable, r_dtype F64 or F32) as in tbs_residual.
+ * Needs no bound workspace, allocates nothing (no device memory, no pinned host memory, no
+ * events) and does not synchronise: asynchronous on the context's stream, whose device must be
+ * the current one.  TBS_E_INVAL if the residual launch of this grid needs more than
+ * TBS_NOALLOC_MAX_BLOCKS workgroups (its launch has ceil(Nx/64) * ceil(Ny/8) * z-chunks of them;
+ * roughly an x-y plane above 3e7 points, or a small tbs_opts.zchunk).  Every call on one GPU
+ * uses that GPU's one buffer, which keeps the last call's values: calls that overlap in time on
+ * one GPU (other streams or threads) race and must be serialised by the caller. */
+#define TBS_NOALLOC_MAX_BLOCKS 65536
+int tbs_residual_noalloc(tbs_ctx* ctx, const double* x, const double* b, void* r, int r_dtype, double* norms);
+
 /* *out = sum_i a_i b_i with FP64 accumulation in a fixed order (bitwise reproducible).
  * dtype F64 or F32.  Synchronises the stream. */
 int tbs_dot(tbs_ctx* ctx, const void* a, const void* b, int dtype, double* out);

@@ -34,7 +34,7 @@ EXPORTS = [
     "tbs_timestep", "tbs_net_create", "tbs_net_destroy", "tbs_net_workspace_bytes", "tbs_net_bind_workspace",
     "tbs_net_set_weights", "tbs_net_get_weights", "tbs_net_set_hparams", "tbs_net_forward",
     "tbs_net_train_step", "tbs_net_conv_layer", "tbs_net_get_grad", "tbs_prof_enable", "tbs_prof_read", "tbs_strerror",
-    "tbs_last_error", "tbs_transform_setup", "tbs_transform_eval", "tbs_transform_interp",
+    "tbs_last_error", "tbs_transform_setup", "tbs_transform_eval", "tbs_transform_interp", "tbs_residual_noalloc",
 ]
 PROF_KINDS = ["apply_f64", "apply_f32", "apply_bf16_f32", "rhs_f64", "rhs_f32", "cg_fused_f64", "cg_fused_f32",
               "cg_fused_f32_bf16p", "residual_f64", "cg_update_f64", "cg_update_f32", "cg_iter_f32",
@@ -75,6 +75,7 @@ _lib.tbs_transform_eval.argtypes = [_vp, _vp, _vp, ctypes.c_int]
 _lib.tbs_transform_interp.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
                                       _dp]
 _lib.tbs_residual.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, _dp, _dp]
+_lib.tbs_residual_noalloc.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, _vp]
 _lib.tbs_dot.argtypes = [_vp, _vp, _vp, ctypes.c_int, _dp]
 _lib.tbs_convert.argtypes = [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int]
 _lib.tbs_cg_begin.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double]
@@ -212,6 +213,16 @@ class Context:
         _check(_lib.tbs_residual(self._h, _ptr(x), _ptr(b), _ptr(r), F64 if r is None else _dtype_code(r),
                                  ctypes.byref(rn), ctypes.byref(bn)), "tbs_residual")
         return rn.value, bn.value
+
+    def residual_noalloc(self, x, b, r=None, norms=None):
+        """Allocation-free residual: writes ||b - A x||, ||b|| into the device tensor `norms`
+        (2 float64 values; allocated here if None) without synchronising; returns `norms`."""
+        import torch
+        if norms is None:
+            norms = torch.empty(2, dtype=torch.float64, device=x.device)
+        _check(_lib.tbs_residual_noalloc(self._h, _ptr(x), _ptr(b), _ptr(r), F64 if r is None else _dtype_code(r),
+                                         _ptr(norms)), "tbs_residual_noalloc")
+        return norms
 
     def dot(self, a, b):
         out = ctypes.c_double()

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -186,10 +187,12 @@ static StencilArgs base_args(const tbs_ctx* c) {
   a.nx = (int)c->nx; a.ny = (int)c->ny; a.nz = (int)c->nz; a.zc = c->zc;
   a.tiles_x = c->tiles_x; a.tiles_y = c->tiles_y; a.nchunks = c->nchunks; a.nblocks = c->nblocks;
   a.t = c->taps;
-  a.part0 = part0(c);
-  a.part1 = part1(c);
-  a.part2 = part2(c);
-  a.part3 = part3(c);
+  if (c->ws) {
+    a.part0 = part0(c);
+    a.part1 = part1(c);
+    a.part2 = part2(c);
+    a.part3 = part3(c);
+  }
   a.order = c->opts.tile_order;
   a.nt_store = c->opts.nt_store;
   return a;
@@ -493,6 +496,74 @@ extern "C" int tbs_residual(tbs_ctx* c, const double* x, const double* b, void* 
   if (rc) return rc;
   if (rnorm) *rnorm = std::sqrt(s.out);
   if (bnorm) *bnorm = std::sqrt(s.out2);
+  return TBS_OK;
+}
+
+// ------------------------------------------------------------------------------------------
+// allocation-free residual: the per-workgroup partial sums and the reduction scalars live in a
+// library-owned static device array instead of the bound workspace
+
+constexpr int kNoAllocMaxBlocks = TBS_NOALLOC_MAX_BLOCKS;
+constexpr size_t kScratchBytes = 256 + 2 * (size_t)kNoAllocMaxBlocks * sizeof(double);  // Scalars, part0, part1
+constexpr int kMaxDevices = 64;
+
+// Host code never passes this name to a kernel: it is a host-side stand-in; the device address
+// of each GPU's copy comes from hipGetSymbolAddress (scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_dev[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device, looked up once per device.
+static int scratch_ptr(void** out) {
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return set_err(TBS_E_INVAL, "device index %d not below %d", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return set_err(TBS_E_HIP, "hipGetSymbolAddress returned a null address");
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return TBS_OK;
+}
+
+extern "C" int tbs_residual_noalloc(tbs_ctx* c, const double* x, const double* b, void* r, int r_dt, double* norms) {
+  if (!c) return set_err(TBS_E_INVAL, "null context");
+  if (!aligned_ptr(x) || !aligned_ptr(b) || (r && !aligned_ptr(r)))
+    return set_err(TBS_E_INVAL, "arrays must be 256-byte aligned device pointers");
+  if (!norms || ((uintptr_t)norms & 7u)) return set_err(TBS_E_INVAL, "norms must be an 8-byte aligned device pointer");
+  if (r && (r == (void*)x || r == (void*)b)) return set_err(TBS_E_INVAL, "r must not alias x or b");
+  if ((void*)norms == (void*)x || (void*)norms == (void*)b || (r && (void*)norms == r))
+    return set_err(TBS_E_INVAL, "norms must not alias the arrays");
+  if (r && r_dt != TBS_F64 && r_dt != TBS_F32) return set_err(TBS_E_INVAL, "r dtype must be F64 or F32");
+  StencilArgs a = base_args(c);
+  const int nb = stencil_blocks(a, M_RESID, 8);
+  if (nb > kNoAllocMaxBlocks)
+    return set_err(TBS_E_INVAL, "residual launch needs %d workgroups, the static buffer holds %d", nb, kNoAllocMaxBlocks);
+  if (c->st) {
+    int sdev = -1, cur = -1;
+    HIPCHK(hipStreamGetDevice(c->st, &sdev));
+    HIPCHK(hipGetDevice(&cur));
+    if (sdev != cur) return set_err(TBS_E_INVAL, "the context's stream is on device %d, device %d is current", sdev, cur);
+  }
+  void* sp = nullptr;
+  int rc = scratch_ptr(&sp);
+  if (rc) return rc;
+  Scalars* sc = (Scalars*)sp;
+  double* p0 = (double*)((char*)sp + 256);
+  double* p1 = p0 + kNoAllocMaxBlocks;
+  a.in0 = x;
+  a.bvec = b;
+  a.out0 = r;
+  a.part0 = p0;
+  a.part1 = p1;
+  a.part2 = a.part3 = nullptr;
+  HIPCHK(launch_resid(a, c->n, c->bc, r_dt == TBS_F32 ? 1 : 0, c->st));
+  HIPCHK(launch_finalize(FIN_NORMS, p0, p1, nb, sc, 0.0, c->st));
+  HIPCHK(launch_norms_out(sc, norms, c->st));
   return TBS_OK;
 }
 

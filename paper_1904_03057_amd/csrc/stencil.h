@@ -70,5 +70,7 @@ enum FinOp { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_DOT = 3, FIN_NORMS =
 // and updates the CG scalars.  FIN_FUSED takes p.q, r.q, q.q and r.r of a CGF launch.
 hipError_t launch_finalize(int op, const double* p0, const double* p1, int count, Scalars* s, double rtol,
                            hipStream_t st, const double* p2 = nullptr, const double* p3 = nullptr);
+// out[0] = sqrt(s->out), out[1] = sqrt(s->out2) (the norms of a FIN_NORMS reduction) in device memory
+hipError_t launch_norms_out(const Scalars* s, double* out, hipStream_t st);
 
 }  // namespace tbs

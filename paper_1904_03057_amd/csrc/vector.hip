@@ -161,6 +161,14 @@ __global__ __launch_bounds__(256) void fill_kernel(uint32_t* __restrict__ x, int
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < nwords; i += stride) x[i] = 0u;
 }
 
+// out[0] = sqrt(r.r), out[1] = sqrt(b.b) of a FIN_NORMS reduction, to device memory
+__global__ void norms_out_kernel(const Scalars* __restrict__ s, double* __restrict__ out) {
+  if (threadIdx.x == 0) {
+    out[0] = sqrt(s->out);
+    out[1] = sqrt(s->out2);
+  }
+}
+
 __global__ __launch_bounds__(1024) void finalize_kernel(int op, const double* __restrict__ p0,
                                                         const double* __restrict__ p1,
                                                         const double* __restrict__ p2,
@@ -336,6 +344,11 @@ hipError_t launch_fill(void* x, int dt, int64_t n, hipStream_t st) {
   const int64_t bytes = n * (dt == 0 ? 8 : (dt == 1 ? 4 : 2));
   const int64_t words = (bytes + 3) / 4;
   hipLaunchKernelGGL(fill_kernel, dim3(vec_blocks(words)), dim3(256), 0, st, (uint32_t*)x, words);
+  return hipGetLastError();
+}
+
+hipError_t launch_norms_out(const Scalars* s, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(norms_out_kernel, dim3(1), dim3(64), 0, st, s, out);
   return hipGetLastError();
 }
 

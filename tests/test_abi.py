@@ -111,3 +111,22 @@ def test_set_opts_validation_without_gpu():
         setattr(o, field, bad)
         assert lib.tbs_set_opts(p, ctypes.byref(o)) == tbs.E_INVAL, field
     lib.tbs_destroy(p)
+
+
+def test_residual_noalloc_validates_before_any_hip_call():
+    lib = tbs.lib()
+    a, b, r, nrm = (ctypes.c_void_p(256 * k) for k in (1, 2, 3, 4))
+    rc, p = _setup(grid=(64, 64, 16), n=2)
+    assert rc == tbs.OK
+    lib.tbs_residual_noalloc.argtypes = [ctypes.c_void_p] * 4 + [ctypes.c_int, ctypes.c_void_p]
+    assert lib.tbs_residual_noalloc(p, a, b, r, tbs.F64, None) == tbs.E_INVAL          # no norms buffer
+    assert lib.tbs_residual_noalloc(p, a, b, r, tbs.F64, ctypes.c_void_p(260)) == tbs.E_INVAL  # misaligned
+    assert lib.tbs_residual_noalloc(p, a, b, a, tbs.F64, nrm) == tbs.E_INVAL            # r aliases x
+    assert lib.tbs_residual_noalloc(p, a, b, r, tbs.BF16, nrm) == tbs.E_INVAL           # bad r dtype
+    lib.tbs_destroy(p)
+    # a plane of 19200 x 2400 points needs 300 * 300 residual workgroups: more than the static buffer holds
+    rc, p = _setup(grid=(64 * 300, 8 * 300, 16), n=2)
+    assert rc == tbs.OK
+    assert lib.tbs_residual_noalloc(p, a, b, r, tbs.F64, nrm) == tbs.E_INVAL
+    assert b"static buffer" in tbs.lib().tbs_last_error()
+    lib.tbs_destroy(p)
