@@ -52,7 +52,7 @@ extern "C" {
 typedef struct tbs_ctx tbs_ctx;
 typedef struct tbs_net tbs_net;
 
-typedef enum { TBS_BC_PERIODIC = 0, TBS_BC_DIRICHLET = 1 } tbs_bc;
+typedef enum { TBS_BC_PERIODIC = 0, TBS_BC_DIRICHLET = 1, TBS_BC_ROBIN = 2 /* tbs_setup_robin only */ } tbs_bc;
 typedef enum { TBS_F64 = 0, TBS_F32 = 1, TBS_BF16 = 2 } tbs_dtype;
 typedef enum {
   TBS_PREC_FP64 = 0,       /* plain FP64 CG */
@@ -74,6 +74,8 @@ typedef struct {
   int coarse_iters;        /* CG iterations of the coarse solve (0 if none) */
   double rel_res_coarse;   /* FP64 relative residual of the coarse-grid guess (NaN if none) */
   int skipped_learned_guess;  /* 1 if a network was passed but not run this step (guess_backoff) */
+  double learned_gamma;    /* multiplier of the network output in the guess u^k + gamma du (energy
+                              test: the A-norm-optimal one; residual test: 1; 0 if not run) */
 } tbs_stats;
 
 typedef struct {
@@ -111,6 +113,14 @@ typedef struct {
                               the network for the next min(2^(k-1), 64) steps (plain guess, no
                               network cost), then test it again; a kept guess resets k.  The
                               counters live in the context; tbs_set_opts resets them. */
+  int guess_test;          /* how tbs_timestep judges the network output du (not in the paper):
+                              0 = energy test (default): with r0 = b - A u^k, the guess is
+                              u^k + gamma du, gamma = r0.du / du.A du (the multiple that minimises the
+                              A-norm of the error; one FP32 apply and two dot products), kept if that
+                              A-norm drops, i.e. 2 gamma r0.du - gamma^2 du.A du > 0; for the backoff
+                              a kept guess that does not halve the plain guess's FP64 residual counts
+                              as a rejection.  1 = residual test: u^k + du is kept if its FP64
+                              residual is smaller than that of u^k. */
 } tbs_opts;
 
 /* ---------------------------------------------------------------- context ---------------- */
@@ -122,6 +132,24 @@ typedef struct {
 int tbs_setup(tbs_ctx** out, const int64_t grid[3], int degree, const double h[3], double tau,
               int bc, void* hip_stream);
 void tbs_destroy(tbs_ctx* ctx);
+
+/* Box domain with the Robin / penalty boundary branch (Sec. 2.2: the Robin condition adds half the
+ * boundary integral of phi psi to the bilinear form; Sec. 2.3: the branch (1/(2 gamma)) int over
+ * the boundary of b_k b_l in the discrete Ritz-Galerkin system, every domain integral restricted
+ * to the box; a small gamma imposes phi = 0 weakly, the Dirichlet-by-penalty of the Sec. 3 leg
+ * example).  The box is [0, Nc_d h_d] per axis and every B-spline whose support meets it is a basis
+ * function: N_d = Nc_d + 1 + 2 floor(n/2) coefficients, index i <-> offset i - floor(n/2).  One
+ * implicit step of du/dt = Lap u + f with du/dn + u / (2 gamma) = 0 solves
+ *     A_R u^{k+1} = Mx My Mz (u^k + tau f),
+ *     A_R = Mx My Mz + tau sum_d (h_d^-2 K_d + h_d^-1 E_d / (2 gamma)) [axis d; M on the others],
+ * divided through by hx hy hz like the rest of the library; M_d, K_d are the box integrals (the
+ * Toeplitz taps except in the first and last 2 floor(n/2) + 1 rows and columns), E_d the products
+ * of the B-splines at the two end points of the axis.  The context then serves tbs_apply, tbs_rhs
+ * (the box mass), tbs_residual, tbs_cg_begin / tbs_cg_step and tbs_timestep (all precisions, the
+ * network guess with zero padding; not the coarse-grid guess) exactly as for TBS_BC_DIRICHLET.
+ * gamma > 0; every N_d >= 4 floor(n/2) + 2 + n (TBS_E_INVAL otherwise). */
+int tbs_setup_robin(tbs_ctx** out, const int64_t grid[3], int degree, const double h[3], double tau,
+                    double gamma, void* hip_stream);
 
 /* Device scratch needed by the solver entry points for precision mode prec (tbs_prec), or, with
  * prec = -1, by tbs_residual / tbs_dot only (partial sums); tbs_apply and tbs_rhs need none.  The
@@ -142,6 +170,20 @@ int tbs_set_opts(tbs_ctx* ctx, const tbs_opts* opts);
  * in_dtype / out_dtype: (F64,F64), (F32,F32), (BF16,F32), (F32,F64) or (BF16,F64); arithmetic
  * is FP64 when out is F64, FP32 otherwise.  Needs no workspace. */
 int tbs_apply(tbs_ctx* ctx, const void* u, int in_dtype, void* y, int out_dtype);
+
+/* Variable coefficients (Sec. 2.3: the diffusion coefficient D and the absorption coefficient
+ * mu_a expanded in the solution's basis, D = sum d_m b_m, mu_a = sum m_m b_m; Sec. 2.4: the
+ * domain branches of the tensor form F(c) = t with the three-index kernels f^{klm}, w^{klm}):
+ *     y_l = sum_k sum_m u_k (m_m f^{klm} + d_m w^{klm}),
+ *     f^{klm} = int b_k b_l b_m,  w^{klm} = int grad b_k . grad b_l b_m  (divided by hx hy hz),
+ * computed on the fly (Sec. 2.5 strategy (c)) by exact cell-wise Gauss quadrature (ceil((3n+1)/2)
+ * points per cell and axis) with sum factorisation.  u, d, m, y: N-element arrays of dtype F64 or
+ * F32 (the arithmetic precision), layout [z][y][x]; u is zero beyond a Dirichlet box, d and m
+ * continue beyond it by their edge values; periodic grids wrap.  With d = tau and m = 1 everywhere
+ * y = A u.  Uses the context's grid, degree, spacings and boundary condition (tau is not used:
+ * d carries it); periodic or Dirichlet solver contexts only (TBS_E_STATE otherwise).  Needs no
+ * workspace; asynchronous. */
+int tbs_apply_varcoef(tbs_ctx* ctx, const void* u, const void* d, const void* m, void* y, int dtype);
 
 /* b = (Mx (x) My (x) Mz)(u_prev + tau q): right-hand side of one implicit Euler step.
  * q may be NULL (f = 0).  dtype F64 or F32 for all three arrays.  Needs no workspace. */
@@ -176,6 +218,11 @@ int tbs_dot(tbs_ctx* ctx, const void* a, const void* b, int dtype, double* out);
  * BF16 -> F32 / F64. */
 int tbs_convert(tbs_ctx* ctx, const void* src, int src_dtype, void* dst, int dst_dtype);
 
+/* Copies `bytes` bytes from src to dst (device, 256-byte aligned, not overlapping) with 16-byte
+ * accesses, four in flight per thread: the device-copy bandwidth reference for the kernels above
+ * (not part of the method).  Asynchronous. */
+int tbs_stream_copy(tbs_ctx* ctx, const void* src, void* dst, size_t bytes);
+
 /* ------------------------------------------------------- CG (Sec. 2.5, step 3) ----------- */
 
 /* Starts CG on A x = b in dtype (F64 or F32): r = b - A x, p = r, with state in the workspace
@@ -194,9 +241,9 @@ int tbs_cg_step(tbs_ctx* ctx, int n_iters, double* rel_res_out, int* iters_out);
 
 /* One implicit Euler step: solves A u_next = M (u_prev + tau q) to ||b - A u|| <= rtol ||b||.
  * u_prev, q (nullable), u_next: FP64 device arrays.  prec selects the arithmetic (tbs_prec).
- * net: optional learned initial guess; its guess is kept only if its FP64 residual is smaller
- * than that of the plain guess u_prev (tbs_opts.guess_backoff: whether a rejected network is
- * skipped on the following steps).  u_next is output only (its prior contents are never read);
+ * net: optional learned initial guess, judged against the plain guess u_prev by the test
+ * tbs_opts.guess_test selects (tbs_opts.guess_backoff: whether a rejected network is skipped on
+ * the following steps).  u_next is output only (its prior contents are never read);
  * it holds the answer on TBS_OK, TBS_W_NOT_CONVERGED and TBS_E_BREAKDOWN and is unspecified
  * after any other error.  Synchronises; fills *stats if not NULL. */
 int tbs_timestep(tbs_ctx* ctx, const double* u_prev, const double* q, double* u_next, int prec,
@@ -286,8 +333,9 @@ int tbs_net_get_grad(const tbs_net* net, float* host, size_t n);
  * written once).  CG launches that found the solve already converged are not counted.
  * Kinds: 0 apply f64, 1 apply f32, 2 apply bf16->f32, 3 rhs f64, 4 rhs f32, 5 cg-fused f64,
  * 6 cg-fused f32, 7 cg-fused f32 with bf16 p, 8 residual f64, 9 cg-update f64, 10 cg-update f32,
- * 11 one-kernel CG iteration f32, 12 one-kernel CG iteration f32 with bf16 p. */
-#define TBS_PROF_KINDS 13
+ * 11 one-kernel CG iteration f32, 12 one-kernel CG iteration f32 with bf16 p, 13 variable-coefficient
+ * apply f64, 14 variable-coefficient apply f32 (bytes: u, d, m read and y written once). */
+#define TBS_PROF_KINDS 15
 int tbs_prof_enable(tbs_ctx* ctx, int on);   /* resets the counters */
 int tbs_prof_read(tbs_ctx* ctx, int kind, double* total_ms, double* total_bytes, int64_t* launches);
 

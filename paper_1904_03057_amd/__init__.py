@@ -23,7 +23,7 @@ import torch  # noqa: E402,F401
 _lib = ctypes.CDLL(LIB_PATH)
 
 OK, E_INVAL, E_NOMEM, E_HIP, E_BREAKDOWN, E_STATE, W_NOT_CONVERGED = 0, -1, -2, -3, -4, -5, 1
-PERIODIC, DIRICHLET = 0, 1
+PERIODIC, DIRICHLET, ROBIN = 0, 1, 2
 F64, F32, BF16 = 0, 1, 2
 PREC_FP64, PREC_FP32, PREC_MIXED, PREC_MIXED_BF16 = 0, 1, 2, 3
 NET_PARAMS = 15169
@@ -35,10 +35,11 @@ EXPORTS = [
     "tbs_net_set_weights", "tbs_net_get_weights", "tbs_net_set_hparams", "tbs_net_forward",
     "tbs_net_train_step", "tbs_net_conv_layer", "tbs_net_get_grad", "tbs_prof_enable", "tbs_prof_read", "tbs_strerror",
     "tbs_last_error", "tbs_transform_setup", "tbs_transform_eval", "tbs_transform_interp", "tbs_residual_noalloc",
+    "tbs_setup_robin", "tbs_apply_varcoef", "tbs_stream_copy",
 ]
 PROF_KINDS = ["apply_f64", "apply_f32", "apply_bf16_f32", "rhs_f64", "rhs_f32", "cg_fused_f64", "cg_fused_f32",
               "cg_fused_f32_bf16p", "residual_f64", "cg_update_f64", "cg_update_f32", "cg_iter_f32",
-              "cg_iter_f32_bf16p"]
+              "cg_iter_f32_bf16p", "varcoef_f64", "varcoef_f32"]
 
 
 class Stats(ctypes.Structure):
@@ -46,7 +47,8 @@ class Stats(ctypes.Structure):
                 ("status", ctypes.c_int), ("rel_res_fp64", ctypes.c_double), ("rel_res0", ctypes.c_double),
                 ("rel_res_plain", ctypes.c_double), ("rel_res_learned", ctypes.c_double),
                 ("used_coarse_guess", ctypes.c_int), ("coarse_iters", ctypes.c_int),
-                ("rel_res_coarse", ctypes.c_double), ("skipped_learned_guess", ctypes.c_int)]
+                ("rel_res_coarse", ctypes.c_double), ("skipped_learned_guess", ctypes.c_int),
+                ("learned_gamma", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -56,11 +58,14 @@ class Opts(ctypes.Structure):
     _fields_ = [("inner_rtol", ctypes.c_double), ("inner_max_iter", ctypes.c_int),
                 ("max_sweeps", ctypes.c_int), ("poll_every", ctypes.c_int), ("zchunk", ctypes.c_int),
                 ("tile_order", ctypes.c_int), ("nt_store", ctypes.c_int), ("fused_cg", ctypes.c_int),
-                ("coarse_guess", ctypes.c_int), ("coarse_rtol", ctypes.c_double), ("guess_backoff", ctypes.c_int)]
+                ("coarse_guess", ctypes.c_int), ("coarse_rtol", ctypes.c_double), ("guess_backoff", ctypes.c_int),
+                ("guess_test", ctypes.c_int)]
 
 
 _vp, _i64p, _dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
 _lib.tbs_setup.argtypes = [ctypes.POINTER(_vp), _i64p, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_int, _vp]
+_lib.tbs_setup_robin.argtypes = [ctypes.POINTER(_vp), _i64p, ctypes.c_int, _dp, ctypes.c_double, ctypes.c_double,
+                                 _vp]
 _lib.tbs_destroy.argtypes = [_vp]
 _lib.tbs_destroy.restype = None
 _lib.tbs_workspace_bytes.argtypes = [_vp, ctypes.c_int]
@@ -70,6 +75,7 @@ _lib.tbs_taps.argtypes = [_vp, _dp, _dp]
 _lib.tbs_set_opts.argtypes = [_vp, ctypes.POINTER(Opts)]
 _lib.tbs_apply.argtypes = [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int]
 _lib.tbs_rhs.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int]
+_lib.tbs_apply_varcoef.argtypes = [_vp, _vp, _vp, _vp, _vp, ctypes.c_int]
 _lib.tbs_transform_setup.argtypes = [ctypes.POINTER(_vp), _i64p, ctypes.c_int, ctypes.c_int, _vp]
 _lib.tbs_transform_eval.argtypes = [_vp, _vp, _vp, ctypes.c_int]
 _lib.tbs_transform_interp.argtypes = [_vp, _vp, _vp, ctypes.c_double, ctypes.c_int, ctypes.POINTER(ctypes.c_int),
@@ -78,6 +84,7 @@ _lib.tbs_residual.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, _dp, _dp]
 _lib.tbs_residual_noalloc.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, _vp]
 _lib.tbs_dot.argtypes = [_vp, _vp, _vp, ctypes.c_int, _dp]
 _lib.tbs_convert.argtypes = [_vp, _vp, ctypes.c_int, _vp, ctypes.c_int]
+_lib.tbs_stream_copy.argtypes = [_vp, _vp, _vp, ctypes.c_size_t]
 _lib.tbs_cg_begin.argtypes = [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double]
 _lib.tbs_cg_step.argtypes = [_vp, ctypes.c_int, _dp, ctypes.POINTER(ctypes.c_int)]
 _lib.tbs_timestep.argtypes = [_vp, _vp, _vp, _vp, ctypes.c_int, ctypes.c_double, ctypes.c_int, _vp,
@@ -191,9 +198,10 @@ class Context:
         return list(m), list(s)
 
     def set_opts(self, inner_rtol=1e-6, inner_max_iter=500, max_sweeps=12, poll_every=4, zchunk=0,
-                 tile_order=0, nt_store=0, fused_cg=1, coarse_guess=0, coarse_rtol=1e-2, guess_backoff=0):
+                 tile_order=0, nt_store=0, fused_cg=1, coarse_guess=0, coarse_rtol=1e-2, guess_backoff=0,
+                 guess_test=0):
         o = Opts(inner_rtol, inner_max_iter, max_sweeps, poll_every, zchunk, tile_order, nt_store, fused_cg,
-                 coarse_guess, coarse_rtol, guess_backoff)
+                 coarse_guess, coarse_rtol, guess_backoff, guess_test)
         _check(_lib.tbs_set_opts(self._h, ctypes.byref(o)), "tbs_set_opts")
         # options can change the workspace layout (partial-sum count, coarse-guess region): the
         # library drops its binding then; rebind the buffer if it still holds the minimum
@@ -204,6 +212,11 @@ class Context:
 
     def apply(self, u, y):
         _check(_lib.tbs_apply(self._h, _ptr(u), _dtype_code(u), _ptr(y), _dtype_code(y)), "tbs_apply")
+
+    def apply_varcoef(self, u, d, m, y):
+        """y = F(u) with the coefficient fields d (diffusion) and m (absorption) in the same basis."""
+        _check(_lib.tbs_apply_varcoef(self._h, _ptr(u), _ptr(d), _ptr(m), _ptr(y), _dtype_code(y)),
+               "tbs_apply_varcoef")
 
     def rhs(self, u_prev, q, b):
         _check(_lib.tbs_rhs(self._h, _ptr(u_prev), _ptr(q), _ptr(b), _dtype_code(b)), "tbs_rhs")
@@ -231,6 +244,13 @@ class Context:
 
     def convert(self, src, dst):
         _check(_lib.tbs_convert(self._h, _ptr(src), _dtype_code(src), _ptr(dst), _dtype_code(dst)), "tbs_convert")
+
+    def stream_copy(self, src, dst):
+        """dst <- src (same byte size) with the library's 16-byte streaming copy kernel."""
+        nb = src.numel() * src.element_size()
+        if dst.numel() * dst.element_size() != nb:
+            raise ValueError("src and dst sizes differ")
+        _check(_lib.tbs_stream_copy(self._h, _ptr(src), _ptr(dst), nb), "tbs_stream_copy")
 
     def cg_begin(self, b, x, rtol):
         _check(_lib.tbs_cg_begin(self._h, _ptr(b), _ptr(x), _dtype_code(x), rtol), "tbs_cg_begin")
@@ -261,6 +281,21 @@ class Context:
         d = st.as_dict()
         d["converged"] = rc == OK
         return d
+
+
+class RobinContext(Context):
+    """Box domain with the Robin / penalty boundary branch (parameter gamma), N_d = Nc_d + 1 + 2 floor(n/2)
+    coefficients per axis; apply, rhs, residual, CG and time steps as on a Context."""
+
+    def __init__(self, grid, degree, h, tau, gamma, stream=None):
+        self._h = ctypes.c_void_p()
+        sh, self.stream = _stream_handle(stream)
+        g = (ctypes.c_int64 * 3)(*grid)
+        hh = (ctypes.c_double * 3)(*h)
+        _check(_lib.tbs_setup_robin(ctypes.byref(self._h), g, degree, hh, tau, gamma, sh), "tbs_setup_robin")
+        self.grid, self.degree, self.h, self.tau, self.bc, self.gamma = tuple(grid), degree, tuple(h), tau, ROBIN, gamma
+        self.shape = (grid[2], grid[1], grid[0])
+        self._ws = None
 
 
 class Transform(Context):

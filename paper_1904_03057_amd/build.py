@@ -17,8 +17,12 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtbs.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["stencil_n1.hip", "stencil_n2.hip", "stencil_n3.hip", "stencil_n4.hip", "stencil_n5.hip", "stencil.hip",
-           "vector.hip", "net.hip", "transfer.hip", "api.cpp"]
+# (source, object name, extra defines): the stencil kernels compile once per degree and boundary
+# condition from one instantiation unit, in parallel with the rest
+STENCIL_UNITS = [("stencil_inst.hip", "stencil_n%d_%s" % (n, b.lower()), ["-DTBS_DEGREE=%d" % n, "-DTBS_BC=BC_%s" % b])
+                 for n in (5, 4, 3, 2, 1) for b in ("ROBIN", "DIRICHLET", "PERIODIC")]
+SOURCES = STENCIL_UNITS + [(f, f, []) for f in ("stencil.hip", "vector.hip", "net.hip", "transfer.hip",
+                                                "varcoef.hip", "api.cpp")]
 
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
@@ -29,9 +33,10 @@ FLAGS = [
 ]
 
 
-def _compile(src, extra):
-    obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-    cmd = [HIPCC] + FLAGS + extra + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(unit, extra):
+    src, name, defs = unit
+    obj = os.path.join(BUILD, name + ".o")
+    cmd = [HIPCC] + FLAGS + defs + extra + ["-x", "hip", "-c", os.path.join(CSRC, src), "-o", obj]
     p = subprocess.run(cmd, capture_output=True, text=True)
     if p.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s\n%s" % (" ".join(cmd), p.stdout, p.stderr))
@@ -41,7 +46,7 @@ def _compile(src, extra):
 def build(jobs=None, save_temps=False, verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     extra = ["-save-temps=obj"] if save_temps else []
-    jobs = jobs or min(8, len(SOURCES))
+    jobs = jobs or min(os.cpu_count() or 8, 16, len(SOURCES))
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(lambda s: _compile(s, extra), SOURCES))
     tmp = LIB + ".tmp"

@@ -17,6 +17,7 @@
 #include "net.h"
 #include "stencil.h"
 #include "transfer.h"
+#include "varcoef.h"
 #include "refine.h"
 
 using namespace tbs;
@@ -74,6 +75,65 @@ static double bspline_val(int p, double x) {
   return acc / fact;
 }
 
+// Gauss-Legendre nodes and weights on [-1, 1]: Newton's method on P_q from the three-term recurrence
+static void gauss_legendre(int q, double* x, double* w) {
+  for (int i = 0; i < q; ++i) {
+    double z = std::cos(M_PI * (i + 0.75) / (q + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = z;  // P_0(z), P_1(z)
+      for (int k = 2; k <= q; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = q * (z * p1 - p0) / (z * z - 1.0);  // P_q'(z)
+      const double dz = p1 / dp;
+      z -= dz;
+      if (std::fabs(dz) < 1e-16) break;
+    }
+    x[i] = z;
+    w[i] = 2.0 / ((1.0 - z * z) * dp * dp);
+  }
+}
+
+// derivative of the degree-p B-spline: difference of two shifted degree p-1 splines (p >= 1)
+static double bspline_der(int p, double x) { return bspline_val(p - 1, x + 0.5) - bspline_val(p - 1, x - 0.5); }
+
+// Corner blocks of the box-domain (Robin / penalty) operator, unit spacing (Sec. 2.2 Robin form,
+// Sec. 2.3 boundary branch): the box mass and stiffness integrals over [0, Nc] differ from the
+// Toeplitz taps only where both B-splines reach past an end, by minus their integral over
+// (-inf, 0]; the boundary matrix is E[r][c] = b(-k_r) b(-k_c).  Rows and columns r, c < z, offsets
+// k = index - floor(n/2); exact up to rounding (n+1 Gauss points on every half-unit piece).
+static void robin_corners(int n, const double h[3], double tau, double gamma, RobinCorner* rb) {
+  const int z = 2 * (n / 2) + 1;
+  double gx[8], gw[8];
+  gauss_legendre(n + 1, gx, gw);
+  std::memset(rb, 0, sizeof(*rb));
+  rb->z = z;
+  const double a[3] = {tau / (h[0] * h[0]), tau / (h[1] * h[1]), tau / (h[2] * h[2])};
+  const double e[3] = {tau / (2.0 * gamma * h[0]), tau / (2.0 * gamma * h[1]), tau / (2.0 * gamma * h[2])};
+  for (int r = 0; r < z; ++r) {
+    for (int c = 0; c < z; ++c) {
+      const double kr = r - n / 2, kc = c - n / 2;
+      double im = 0.0, ik = 0.0;
+      for (int piece = 0; piece < 2 * (n + 3); ++piece) {  // [-(n+3), 0] in half-unit pieces
+        const double lo = -(n + 3) + 0.5 * piece, mid = lo + 0.25;
+        for (int g = 0; g < n + 1; ++g) {
+          const double x = mid + 0.25 * gx[g], w = 0.25 * gw[g];
+          im += w * bspline_val(n, x - kr) * bspline_val(n, x - kc);
+          ik += w * bspline_der(n, x - kr) * bspline_der(n, x - kc);
+        }
+      }
+      const double E = bspline_val(n, -kr) * bspline_val(n, -kc);
+      const int i = r * kRobinMaxZ + c;
+      rb->cm[i] = -im;
+      rb->cvx[i] = -im - a[0] * ik + e[0] * E;
+      rb->cwy[i] = -a[1] * ik + e[1] * E;
+      rb->cwz[i] = -a[2] * ik + e[2] * E;
+    }
+  }
+}
+
 static void make_taps(int n, double* m, double* s) {
   const int p = 2 * n + 1;
   for (int k = 0; k <= n; ++k) {
@@ -90,6 +150,8 @@ struct tbs_ctx {
   int64_t nx, ny, nz, N;
   int n, bc;
   double h[3], tau;
+  double gamma;      // Robin / penalty parameter (TBS_BC_ROBIN)
+  RobinCorner rb;    // its corner blocks
   hipStream_t st;
   Taps taps;
   int tiles_x, tiles_y, nchunks, zc, nblocks, nparts;
@@ -195,6 +257,7 @@ static StencilArgs base_args(const tbs_ctx* c) {
   }
   a.order = c->opts.tile_order;
   a.nt_store = c->opts.nt_store;
+  if (c->bc == TBS_BC_ROBIN) a.rb = c->rb;
   return a;
 }
 
@@ -238,6 +301,30 @@ extern "C" int tbs_setup(tbs_ctx** out, const int64_t grid[3], int degree, const
   c->opts.coarse_guess = 0;
   c->opts.coarse_rtol = 1e-2;
   *out = c;
+  return TBS_OK;
+}
+
+// Box domain with the Robin / penalty boundary branch (Sec. 2.2, Sec. 2.3): N_d = Nc_d + 1 + 2 floor(n/2)
+// coefficients per axis; the stencil kernels run with truncated bands plus the corner blocks.
+extern "C" int tbs_setup_robin(tbs_ctx** out, const int64_t grid[3], int degree, const double h[3], double tau,
+                               double gamma, void* hip_stream) {
+  if (!out || !grid || !h) return set_err(TBS_E_INVAL, "null argument");
+  *out = nullptr;
+  if (!(gamma > 0.0) || !std::isfinite(gamma)) return set_err(TBS_E_INVAL, "gamma must be positive and finite");
+  if (degree < 1 || degree > 5) return set_err(TBS_E_INVAL, "degree %d not in 1..5", degree);
+  const int z = 2 * (degree / 2) + 1;
+  // the two corner zones and a band apart (the z-pass reuses its corner accumulators from the low end
+  // to the high end), so no spline spans the box either
+  const int64_t nmin = 2 * z + degree;
+  for (int d = 0; d < 3; ++d)
+    if (grid[d] < nmin) return set_err(TBS_E_INVAL, "grid[%d]=%lld < %lld for a Robin box of degree %d", d,
+                                       (long long)grid[d], (long long)nmin, degree);
+  int rc = tbs_setup(out, grid, degree, h, tau, TBS_BC_DIRICHLET, hip_stream);
+  if (rc) return rc;
+  tbs_ctx* c = *out;
+  c->bc = TBS_BC_ROBIN;
+  c->gamma = gamma;
+  robin_corners(degree, h, tau, gamma, &c->rb);
   return TBS_OK;
 }
 
@@ -368,15 +455,17 @@ extern "C" int tbs_set_opts(tbs_ctx* c, const tbs_opts* o) {
   if (!o) {
     c->opts.inner_rtol = 1e-6; c->opts.inner_max_iter = 500; c->opts.max_sweeps = 12; c->opts.poll_every = 4;
     c->opts.zchunk = 0; c->opts.tile_order = 0; c->opts.nt_store = 0; c->opts.fused_cg = 1;
-    c->opts.coarse_guess = 0; c->opts.coarse_rtol = 1e-2; c->opts.guess_backoff = 0;
+    c->opts.coarse_guess = 0; c->opts.coarse_rtol = 1e-2; c->opts.guess_backoff = 0; c->opts.guess_test = 0;
   } else {
     if (!(o->inner_rtol > 0 && o->inner_rtol < 1) || o->inner_max_iter < 1 || o->max_sweeps < 1 ||
         o->poll_every < 1 || o->zchunk < 0 || o->tile_order < 0 || o->tile_order > 1 || o->nt_store < 0 ||
         o->nt_store > 1 || o->fused_cg < 0 || o->fused_cg > 1 || o->coarse_guess < 0 || o->coarse_guess > 1 ||
-        !(o->coarse_rtol > 0 && o->coarse_rtol < 1) || o->guess_backoff < 0 || o->guess_backoff > 1)
+        !(o->coarse_rtol > 0 && o->coarse_rtol < 1) || o->guess_backoff < 0 || o->guess_backoff > 1 ||
+        o->guess_test < 0 || o->guess_test > 1)
       return set_err(TBS_E_INVAL, "bad options");
     if (o->coarse_guess) {
       if (c->transform_degree) return set_err(TBS_E_INVAL, "coarse guess on a transform context");
+      if (c->bc == TBS_BC_ROBIN) return set_err(TBS_E_INVAL, "coarse guess on a Robin box");
       if (c->n % 2 == 0) return set_err(TBS_E_INVAL, "coarse guess needs an odd degree (nested dyadic spaces)");
       const int64_t g[3] = {c->nx, c->ny, c->nz};
       for (int d = 0; d < 3; ++d) {
@@ -462,6 +551,49 @@ extern "C" int tbs_rhs(tbs_ctx* c, const void* u_prev, const void* q, void* b, i
   const double e = dt == TBS_F64 ? 8 : 4;
   const int ps = prof_begin(c, dt == TBS_F64 ? 3 : 4, -1, (double)c->N * e * (q ? 3 : 2));
   HIPCHK(launch_rhs(a, c->n, c->bc, dt, c->st));
+  prof_end(c, ps);
+  return TBS_OK;
+}
+
+// Variable-coefficient operator (Sec. 2.3 coefficient expansion, Sec. 2.4 three-index kernels):
+// cell-wise Gauss quadrature tables and the strip geometry of the sum-factorised kernel.
+extern "C" int tbs_apply_varcoef(tbs_ctx* c, const void* u, const void* d, const void* m, void* y, int dt) {
+  if (!c) return set_err(TBS_E_INVAL, "null context");
+  if (c->transform_degree || c->bc == TBS_BC_ROBIN)
+    return set_err(TBS_E_STATE, "the variable-coefficient operator needs a periodic or Dirichlet solver context");
+  if (!aligned_ptr(u) || !aligned_ptr(d) || !aligned_ptr(m) || !aligned_ptr(y))
+    return set_err(TBS_E_INVAL, "arrays must be 256-byte aligned device pointers");
+  if (y == u || y == d || y == m) return set_err(TBS_E_INVAL, "y must not alias the inputs");
+  if (dt != TBS_F64 && dt != TBS_F32) return set_err(TBS_E_INVAL, "varcoef dtype must be F64 or F32");
+  const int n = c->n, Q = (3 * n + 2) / 2;
+  VarcoefArgs a{};
+  a.nx = (int)c->nx; a.ny = (int)c->ny; a.nz = (int)c->nz;
+  a.tiles_x = (int)((c->nx + vc_tile_x(n) - 1) / vc_tile_x(n));
+  a.tiles_y = (int)((c->ny + kVcTileY - 1) / kVcTileY);
+  // about 16384 single-wave workgroups, z-chunks of at least 16 planes
+  const int64_t strips = (int64_t)a.tiles_x * a.tiles_y;
+  int64_t chunks = std::min<int64_t>((16384 + strips - 1) / strips, std::max<int64_t>(1, c->nz / 16));
+  a.zc = (int)((c->nz + chunks - 1) / chunks);
+  a.nchunks = (int)((c->nz + a.zc - 1) / a.zc);
+  a.nblocks = a.tiles_x * a.tiles_y * a.nchunks;
+  a.c = u; a.d = d; a.m = m; a.y = y;
+  double gx[kVcMaxQ], gw[kVcMaxQ];
+  gauss_legendre(Q, gx, gw);
+  for (int q = 0; q < Q; ++q) {
+    const double sq = 0.5 * (1.0 + gx[q]);  // Gauss point in the unit cell
+    a.w[q] = 0.5 * gw[q];
+    for (int t = 0; t <= n; ++t) {
+      const double x = sq + 0.5 * (n - 1) - t;  // distance from the t-th B-spline's centre
+      a.bv[q * kVcMaxB + t] = bspline_val(n, x);
+      a.bd[q * kVcMaxB + t] = bspline_der(n, x);
+    }
+  }
+  a.ihx2 = 1.0 / (c->h[0] * c->h[0]);
+  a.ihy2 = 1.0 / (c->h[1] * c->h[1]);
+  a.ihz2 = 1.0 / (c->h[2] * c->h[2]);
+  const double esz = dt == TBS_F64 ? 8 : 4;
+  const int ps = prof_begin(c, dt == TBS_F64 ? 13 : 14, -1, (double)c->N * 4 * esz);
+  HIPCHK(launch_varcoef(a, n, c->bc, dt == TBS_F64 ? 0 : 1, c->st));
   prof_end(c, ps);
   return TBS_OK;
 }
@@ -579,6 +711,17 @@ extern "C" int tbs_dot(tbs_ctx* c, const void* a, const void* b, int dt, double*
   rc = read_scal(c, SC_AUX, &s);
   if (rc) return rc;
   *out = s.out;
+  return TBS_OK;
+}
+
+extern "C" int tbs_stream_copy(tbs_ctx* c, const void* src, void* dst, size_t bytes) {
+  if (!c) return set_err(TBS_E_INVAL, "null context");
+  if (!aligned_ptr(src) || !aligned_ptr(dst)) return set_err(TBS_E_INVAL, "arrays must be 256-byte aligned device pointers");
+  if (src == dst) return set_err(TBS_E_INVAL, "src and dst must differ");
+  const char* s = (const char*)src;
+  const char* d = (const char*)dst;
+  if (s < d + bytes && d < s + bytes) return set_err(TBS_E_INVAL, "src and dst overlap");
+  HIPCHK(launch_stream_copy(src, dst, (int64_t)bytes, c->st));
   return TBS_OK;
 }
 
@@ -859,28 +1002,62 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     const int64_t grid[3] = {c->nx, c->ny, c->nz};
     rc = tbs_net_guess_internal(g, grid, c->bc == TBS_BC_PERIODIC, c->tau, c->st, u_prev, q, &du);
     if (rc) return rc;
-    HIPCHK(launch_guess_combine(u_next, u_prev, du, c->N, c->st));
-    have_x = true;
-    rc = fp64_relres(c, u_next, b64, &st.rel_res_learned);
-    if (rc) return rc;
-    if (prec == TBS_PREC_MIXED || prec == TBS_PREC_MIXED_BF16) {
-      rc = resid_async(c, u_prev, b64, c->ws + L.off[1], TBS_F32, SC_AUX, FIN_NORMS, 0.0);
+    const bool refined = (prec == TBS_PREC_MIXED || prec == TBS_PREC_MIXED_BF16);
+    if (c->opts.guess_test == 0) {
+      // energy test: r0 = b - A u^k (FP64 kernel, kept as FP32 in the first sweep's residual array),
+      // A du in FP32, gamma = r0.du / du.A du minimises ||x* - (u^k + gamma du)||_A, and the A-norm of
+      // the error drops by 2 gamma r0.du - gamma^2 du.A du (= (r0.du)^2 / du.A du)
+      float* r0 = (float*)(c->ws + L.off[1]);
+      float* adu = (float*)(c->ws + L.off[refined ? 5 : 4]);
+      rc = resid_async(c, u_prev, b64, r0, TBS_F32, SC_AUX, FIN_NORMS, 0.0);
       if (rc) return rc;
+      StencilArgs a = base_args(c);
+      a.in0 = du;
+      a.out0 = adu;
+      HIPCHK(launch_apply(a, c->n, c->bc, 1, 1, c->st));
+      HIPCHK(launch_dot(r0, du, c->N, 1, part0(c), c->st));
+      HIPCHK(launch_finalize(FIN_DOT, part0(c), nullptr, kVecBlocks, scal(c, 2), 0.0, c->st));
+      HIPCHK(launch_dot(du, adu, c->N, 1, part0(c), c->st));
+      HIPCHK(launch_finalize(FIN_DOT, part0(c), nullptr, kVecBlocks, scal(c, 3), 0.0, c->st));
+      Scalars d1, d2;
       rc = read_scal(c, SC_AUX, &res0);
+      if (!rc) rc = read_scal(c, 2, &d1);
+      if (!rc) rc = read_scal(c, 3, &d2);
       if (rc) return rc;
       st.rel_res_plain = res0.out2 > 0 ? std::sqrt(res0.out / res0.out2) : std::sqrt(res0.out);
+      const double gam = (d2.out > 0.0 && std::isfinite(d1.out / d2.out)) ? d1.out / d2.out : 0.0;
+      const double drop = 2.0 * gam * d1.out - gam * gam * d2.out;
+      st.learned_gamma = gam;
+      if (drop > 0.0 && std::isfinite(drop)) {
+        HIPCHK(launch_guess_combine(u_next, u_prev, du, c->N, gam, c->st));
+        have_x = true;
+        st.used_learned_guess = 1;
+      } else {
+        have_res0 = refined;  // r0 and its norms are the first sweep's residual
+      }
     } else {
-      rc = fp64_relres(c, u_prev, b64, &st.rel_res_plain);
+      // residual test: u^k + du is kept if its FP64 residual is smaller than that of u^k
+      HIPCHK(launch_guess_combine(u_next, u_prev, du, c->N, 1.0, c->st));
+      have_x = true;
+      st.learned_gamma = 1.0;
+      rc = fp64_relres(c, u_next, b64, &st.rel_res_learned);
       if (rc) return rc;
-    }
-    if (st.rel_res_learned < st.rel_res_plain) {
-      st.used_learned_guess = 1;
-      c->guess_rejects = 0;
-    } else {
-      have_x = false;  // back to the plain guess u_prev
-      have_res0 = (prec == TBS_PREC_MIXED || prec == TBS_PREC_MIXED_BF16);
-      ++c->guess_rejects;
-      if (c->opts.guess_backoff) c->guess_wait = 1 << std::min(c->guess_rejects - 1, 6);
+      if (refined) {
+        rc = resid_async(c, u_prev, b64, c->ws + L.off[1], TBS_F32, SC_AUX, FIN_NORMS, 0.0);
+        if (rc) return rc;
+        rc = read_scal(c, SC_AUX, &res0);
+        if (rc) return rc;
+        st.rel_res_plain = res0.out2 > 0 ? std::sqrt(res0.out / res0.out2) : std::sqrt(res0.out);
+      } else {
+        rc = fp64_relres(c, u_prev, b64, &st.rel_res_plain);
+        if (rc) return rc;
+      }
+      if (st.rel_res_learned < st.rel_res_plain) {
+        st.used_learned_guess = 1;
+      } else {
+        have_x = false;  // back to the plain guess u_prev
+        have_res0 = refined;
+      }
     }
   }
 
@@ -962,6 +1139,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     if (rc) return rc;
     st.rel_res0 = s.bb > 0 ? std::sqrt(s.rr0 / s.bb) : 0.0;
     if (!g && !st.used_coarse_guess && std::isnan(st.rel_res_coarse)) st.rel_res_plain = st.rel_res0;
+    if (st.used_learned_guess) st.rel_res_learned = st.rel_res0;
     int nit = 0;
     result = cg_loop(c, A, 0, 0, max_iter, &nit);
     st.iters = nit;
@@ -1017,6 +1195,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
       if (sweeps == 0) {
         st.rel_res0 = rel;
         if (!g && std::isnan(st.rel_res_coarse)) st.rel_res_plain = rel;
+        if (st.used_learned_guess) st.rel_res_learned = rel;
       }
       st.rel_res_fp64 = rel;
       if (!std::isfinite(rel)) { result = set_err(TBS_E_BREAKDOWN, "non-finite residual"); break; }
@@ -1046,6 +1225,18 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     if (rc) return rc;
     st.iters = total;
     st.sweeps = sweeps;
+  }
+  if (g) {
+    // backoff bookkeeping: a rejected guess counts, and so (energy test) does a kept one that did not
+    // halve the plain guess's residual: it cannot save the iterations its network costs
+    const bool paid = st.used_learned_guess &&
+                      (c->opts.guess_test != 0 || st.rel_res_learned <= 0.5 * st.rel_res_plain);
+    if (paid) {
+      c->guess_rejects = 0;
+    } else {
+      ++c->guess_rejects;
+      if (c->opts.guess_backoff) c->guess_wait = 1 << std::min(c->guess_rejects - 1, 6);
+    }
   }
   st.status = result;
   if (stats) *stats = st;

@@ -32,7 +32,20 @@ struct Scalars {
 // CG1: one half of a Hestenes-Stiefel iteration (p, x update, q = A p, p.q); CGF: a whole iteration
 // in one kernel (r update, p, x update, q = A p and the dot products p.q, r.q, q.q, r.r).
 enum Mode { M_APPLY = 0, M_RHS = 1, M_CG1 = 2, M_RESID = 3, M_CGF = 4 };
-enum Bc { BC_PERIODIC = 0, BC_DIRICHLET = 1 };
+enum Bc { BC_PERIODIC = 0, BC_DIRICHLET = 1, BC_ROBIN = 2 };
+
+// Robin / penalty boundary on a box (BC_ROBIN): every 1-D factor of the operator is the truncated
+// Toeplitz band plus a z x z corner block at each end (the high end mirrors the low end: row N-1-r,
+// column N-1-c holds entry [r][c]).  cm: mass corner; cvx: corner of the x-pass's (Mx + Wx);
+// cwy, cwz: corners of Wy, Wz; W_d = tau (h_d^-2 K_d + h_d^-1 E_d / (2 gamma)).  Row-major z x z.
+constexpr int kRobinMaxZ = 5;
+struct RobinCorner {
+  int z;
+  double cm[kRobinMaxZ * kRobinMaxZ];
+  double cvx[kRobinMaxZ * kRobinMaxZ];
+  double cwy[kRobinMaxZ * kRobinMaxZ];
+  double cwz[kRobinMaxZ * kRobinMaxZ];
+};
 
 struct StencilArgs {
   int nx, ny, nz, zc;          // grid size and planes per z-chunk
@@ -54,6 +67,7 @@ struct StencilArgs {
   int first;                   // CG1, CGF: first iteration (p = r)
   int order;                   // tile order: 0 x-tiles fastest, 1 y-tiles fastest
   int nt_store;                // 1: outputs written with non-temporal stores
+  RobinCorner rb;              // BC_ROBIN corner blocks
 };
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }

@@ -35,10 +35,18 @@ constexpr int stencil_tile_y(int mode, int compute_bytes) {
   return compute_bytes == 4 ? ((mode == M_APPLY) ? 32 : (mode == M_CG1 ? STENCIL_CG_TY : (mode == M_CGF ? STENCIL_CGF_TY : 16)))
                             : (mode == M_RESID ? STENCIL_RESID_TY : 16);
 }
-// One stencil launch of degree N for a (mode, input, compute, output) type combination; defined
-// in stencil_kernel.h and instantiated per degree in stencil_n<N>.hip.
+// One stencil launch of degree N for a (mode, input, compute, output) type combination and
+// boundary condition BC; defined in stencil_kernel.h and instantiated per degree and boundary
+// condition by stencil_inst.hip.
+template <int N, int MODE, typename Tin, typename Tc, typename Tout, int BC>
+hipError_t launch_bcx(const StencilArgs& a, bool vec, hipStream_t st);
+
 template <int N, int MODE, typename Tin, typename Tc, typename Tout>
-hipError_t launch_bc(const StencilArgs& a, int bc, bool vec, hipStream_t st);
+inline hipError_t launch_bc(const StencilArgs& a, int bc, bool vec, hipStream_t st) {
+  if (bc == BC_PERIODIC) return launch_bcx<N, MODE, Tin, Tc, Tout, BC_PERIODIC>(a, vec, st);
+  if (bc == BC_ROBIN) return launch_bcx<N, MODE, Tin, Tc, Tout, BC_ROBIN>(a, vec, st);
+  return launch_bcx<N, MODE, Tin, Tc, Tout, BC_DIRICHLET>(a, vec, st);
+}
 
 // Number of workgroups (= partial sums written) of a stencil launch of this mode.
 int stencil_blocks(const StencilArgs& a, int mode, int compute_bytes);
@@ -61,7 +69,9 @@ hipError_t launch_dot(const void* a, const void* b, int64_t n, int dt, double* p
 hipError_t launch_convert(const void* src, int sdt, void* dst, int ddt, int64_t n, hipStream_t st);
 hipError_t launch_add_f32_to_f64(double* x, const float* d, int64_t n, hipStream_t st);
 hipError_t launch_fill(void* x, int dt, int64_t n, hipStream_t st);  // zero fill
-hipError_t launch_guess_combine(double* x, const double* u, const float* du, int64_t n, hipStream_t st);
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t nbytes, hipStream_t st);
+hipError_t launch_guess_combine(double* x, const double* u, const float* du, int64_t n, double scale,
+                                hipStream_t st);  // x = u + scale du
 
 // finalize kernels (single block, fixed-order reduction of partial sums)
 enum FinOp { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_DOT = 3, FIN_NORMS = 4, FIN_CLEAR_PENDING = 5,

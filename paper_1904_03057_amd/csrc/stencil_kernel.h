@@ -72,8 +72,24 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
   constexpr int RQD = FUSED ? N + 2 : 1;
   __shared__ Tc rring[FUSED ? RQD * TY * TX : 1];
   __shared__ double red[4][4 * WX];
+  // BC_ROBIN: corner blocks in compute precision (cm, cvx, cwy, cwz, each kRobinMaxZ^2)
+  constexpr int RBT = kRobinMaxZ * kRobinMaxZ;
+  __shared__ Tc rbt[BC == BC_ROBIN ? 4 * RBT : 1];
 
   if (CG && a.scal->done) return;
+
+  if constexpr (BC == BC_ROBIN) {
+    // static indices only (uniform loads of the argument block); read after the loop's first barrier
+    if (threadIdx.x == 0) {
+#pragma unroll
+      for (int i = 0; i < RBT; ++i) {
+        rbt[i] = (Tc)a.rb.cm[i];
+        rbt[RBT + i] = (Tc)a.rb.cvx[i];
+        rbt[2 * RBT + i] = (Tc)a.rb.cwy[i];
+        rbt[3 * RBT + i] = (Tc)a.rb.cwz[i];
+      }
+    }
+  }
 
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -273,6 +289,13 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
   for (int s = 0; s < T; ++s)
 #pragma unroll
     for (int i = 0; i < RPW; ++i) acc[s][i] = (Tc)0;
+  // BC_ROBIN: z-corner contributions to the output planes j-th from an end, j < ZM
+  constexpr int ZM = BC == BC_ROBIN ? 2 * (N / 2) + 1 : 1;
+  Tc zacc[ZM][RPW];
+#pragma unroll
+  for (int j = 0; j < ZM; ++j)
+#pragma unroll
+    for (int i = 0; i < RPW; ++i) zacc[j][i] = (Tc)0;
 
   const int gxo = x0 + col;
   const bool colown = gxo < nx;
@@ -309,6 +332,27 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
             U = fmad(m[j], sm, U);
             Vv = fmad(mx[j], sm, Vv);
           }
+          if constexpr (BC == BC_ROBIN) {
+            // corner blocks of Mx and Mx + Wx: output column gx in the first / last z columns
+            constexpr int zr = 2 * (N / 2) + 1;
+            const int gx = x0 + col;
+            if (gx < zr) {
+#pragma unroll
+              for (int cc = 0; cc < zr; ++cc) {
+                const Tc v = row[cc - gx];
+                U = fmad(rbt[gx * kRobinMaxZ + cc], v, U);
+                Vv = fmad(rbt[RBT + gx * kRobinMaxZ + cc], v, Vv);
+              }
+            } else if (gx >= nx - zr && gx < nx) {
+              const int rr = nx - 1 - gx;
+#pragma unroll
+              for (int cc = 0; cc < zr; ++cc) {
+                const Tc v = row[rr - cc];
+                U = fmad(rbt[rr * kRobinMaxZ + cc], v, U);
+                Vv = fmad(rbt[RBT + rr * kRobinMaxZ + cc], v, Vv);
+              }
+            }
+          }
           su[r * TX + col] = U;
           sv[r * TX + col] = Vv;
         }
@@ -336,6 +380,27 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
               Rr = fmad(ays[j], pu, Rr);
             }
           }
+          if constexpr (BC == BC_ROBIN) {
+            // corner blocks of My (on U, V) and Wy (on U): output row gy in the first / last z rows
+            // (wave-uniform); the x-pass results of the other rows are read back from LDS
+            constexpr int zr = 2 * (N / 2) + 1;
+            const int gy = y0 + wave * RPW + i;
+            if (gy < zr || (gy >= ny - zr && gy < ny)) {
+              const bool lo = gy < zr;
+              const int rr = lo ? gy : ny - 1 - gy;
+#pragma unroll
+              for (int cc = 0; cc < zr; ++cc) {
+                const int sr = (lo ? cc : ny - 1 - cc) - y0 + N;  // staged row of the input row
+                const Tc Uc = su[sr * TX + col];
+                const Tc cmv = rbt[rr * kRobinMaxZ + cc];
+                P = fmad(cmv, Uc, P);
+                if (MODE != M_RHS) {
+                  Rr = fmad(cmv, sv[sr * TX + col], Rr);
+                  Rr = fmad(rbt[2 * RBT + rr * kRobinMaxZ + cc], Uc, Rr);
+                }
+              }
+            }
+          }
           // plane k adds to outputs k+d, d = -N..N, held in ring slot (ph + d) mod T
 #pragma unroll
           for (int d = -N; d <= N; ++d) {
@@ -348,12 +413,41 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
               acc[s][i] = fmad(azs[ad], P, acc[s][i]);
             }
           }
+          if constexpr (BC == BC_ROBIN) {
+            // corner blocks of Mz (on R) and Wz (on P): an input plane k among the first / last z
+            // planes adds to the output plane j-th from the same end (j < z) through zacc[j], which
+            // the output step adds in and clears (the low end's are all cleared before the high
+            // end's first input plane: nz >= 2z + n)
+            if (k < ZM || k >= nz - ZM) {
+              const int ri = k < ZM ? k : nz - 1 - k;
+#pragma unroll
+              for (int j = 0; j < ZM; ++j) {
+                zacc[j][i] = fmad(rbt[j * kRobinMaxZ + ri], MODE == M_RHS ? P : Rr, zacc[j][i]);
+                if (MODE != M_RHS) zacc[j][i] = fmad(rbt[3 * RBT + j * kRobinMaxZ + ri], P, zacc[j][i]);
+              }
+            }
+          }
         }
       }
       // output plane o = k - N is complete
       {
         const int so = (ph - N + 3 * T) % T;
         const int o = k - N;
+        Tc zadd[BC == BC_ROBIN ? RPW : 1];
+        if constexpr (BC == BC_ROBIN) {
+          const int zj = (o >= 0 && o < ZM) ? o : ((o >= nz - ZM && o < nz) ? nz - 1 - o : -1);
+#pragma unroll
+          for (int i = 0; i < RPW; ++i) {
+            zadd[i] = (Tc)0;
+#pragma unroll
+            for (int j = 0; j < ZM; ++j) {
+              if (j == zj) {
+                zadd[i] = zacc[j][i];
+                zacc[j][i] = (Tc)0;
+              }
+            }
+          }
+        }
         if (o >= z0) {
           const int64_t obase = (int64_t)o * plane;
           const int qo = ((o % QD) + QD) % QD;
@@ -362,7 +456,8 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
             const int gy = y0 + wave * RPW + i;
             if (colown && gy < ny) {
               const int64_t gi = obase + (int64_t)gy * nx + gxo;
-              const Tc val = acc[so][i];
+              Tc val = acc[so][i];
+              if constexpr (BC == BC_ROBIN) val += zadd[i];
               if (MODE == M_APPLY || MODE == M_RHS) {
                 if (a.nt_store) Io<Tout>::template st_nt<Tc>(a.out0, gi, val);
                 else Io<Tout>::template st<Tc>(a.out0, gi, val);
@@ -424,8 +519,10 @@ template <int MODE, typename Tc> constexpr int tile_wx() {
   return (MODE == M_APPLY && sizeof(Tc) == 4) ? STENCIL_APPLY_WX : 1;
 }
 
-template <int N, int MODE, typename Tin, typename Tc, typename Tout>
-hipError_t launch_bc(const StencilArgs& a0, int bc, bool vec, hipStream_t st) {
+// One launch for boundary condition BC (one object per degree and boundary condition, so the
+// instances compile in parallel; stencil.h dispatches on the run-time boundary condition).
+template <int N, int MODE, typename Tin, typename Tc, typename Tout, int BC>
+hipError_t launch_bcx(const StencilArgs& a0, bool vec, hipStream_t st) {
   constexpr int TY = tile_y<MODE, Tc>();
   constexpr int WX = tile_wx<MODE, Tc>();
   StencilArgs a = a0;  // geometry for this tile shape
@@ -433,37 +530,30 @@ hipError_t launch_bc(const StencilArgs& a0, int bc, bool vec, hipStream_t st) {
   a.tiles_y = (a.ny + TY - 1) / TY;
   a.nblocks = a.tiles_x * a.tiles_y * a.nchunks;
   dim3 grid(a.nblocks), block(256 * WX);
-  if (vec) {
-    if (bc == BC_PERIODIC)
-      hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC_PERIODIC, true, WX>), grid, block, 0, st, a);
-    else
-      hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC_DIRICHLET, true, WX>), grid, block, 0, st, a);
-  } else {
-    if (bc == BC_PERIODIC)
-      hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC_PERIODIC, false, WX>), grid, block, 0, st, a);
-    else
-      hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC_DIRICHLET, false, WX>), grid, block, 0, st, a);
-  }
+  if (vec)
+    hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC, true, WX>), grid, block, 0, st, a);
+  else
+    hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC, false, WX>), grid, block, 0, st, a);
   return hipGetLastError();
 }
 
 }  // namespace tbs
 
-// Every (mode, dtype) combination the dispatch in stencil.hip uses, for degree N.
-#define TBS_STENCIL_INSTANTIATE(N)                                                                     \
-  namespace tbs {                                                                                      \
-  template hipError_t launch_bc<N, M_APPLY, double, double, double>(const StencilArgs&, int, bool, hipStream_t); \
-  template hipError_t launch_bc<N, M_APPLY, float, float, float>(const StencilArgs&, int, bool, hipStream_t);    \
-  template hipError_t launch_bc<N, M_APPLY, uint16_t, float, float>(const StencilArgs&, int, bool, hipStream_t); \
-  template hipError_t launch_bc<N, M_APPLY, float, double, double>(const StencilArgs&, int, bool, hipStream_t);  \
-  template hipError_t launch_bc<N, M_APPLY, uint16_t, double, double>(const StencilArgs&, int, bool, hipStream_t); \
-  template hipError_t launch_bc<N, M_RHS, double, double, double>(const StencilArgs&, int, bool, hipStream_t);   \
-  template hipError_t launch_bc<N, M_RHS, float, float, float>(const StencilArgs&, int, bool, hipStream_t);      \
-  template hipError_t launch_bc<N, M_CG1, double, double, double>(const StencilArgs&, int, bool, hipStream_t);   \
-  template hipError_t launch_bc<N, M_CG1, float, float, float>(const StencilArgs&, int, bool, hipStream_t);      \
-  template hipError_t launch_bc<N, M_CG1, uint16_t, float, float>(const StencilArgs&, int, bool, hipStream_t);   \
-  template hipError_t launch_bc<N, M_CGF, float, float, float>(const StencilArgs&, int, bool, hipStream_t);      \
-  template hipError_t launch_bc<N, M_CGF, uint16_t, float, float>(const StencilArgs&, int, bool, hipStream_t);   \
-  template hipError_t launch_bc<N, M_RESID, double, double, double>(const StencilArgs&, int, bool, hipStream_t); \
-  template hipError_t launch_bc<N, M_RESID, double, double, float>(const StencilArgs&, int, bool, hipStream_t);  \
+// Every (mode, dtype) combination the dispatch in stencil.hip uses, for degree N and boundary BC.
+#define TBS_STENCIL_INSTANTIATE(N, BC)                                                                        \
+  namespace tbs {                                                                                             \
+  template hipError_t launch_bcx<N, M_APPLY, double, double, double, BC>(const StencilArgs&, bool, hipStream_t);   \
+  template hipError_t launch_bcx<N, M_APPLY, float, float, float, BC>(const StencilArgs&, bool, hipStream_t);      \
+  template hipError_t launch_bcx<N, M_APPLY, uint16_t, float, float, BC>(const StencilArgs&, bool, hipStream_t);   \
+  template hipError_t launch_bcx<N, M_APPLY, float, double, double, BC>(const StencilArgs&, bool, hipStream_t);    \
+  template hipError_t launch_bcx<N, M_APPLY, uint16_t, double, double, BC>(const StencilArgs&, bool, hipStream_t); \
+  template hipError_t launch_bcx<N, M_RHS, double, double, double, BC>(const StencilArgs&, bool, hipStream_t);     \
+  template hipError_t launch_bcx<N, M_RHS, float, float, float, BC>(const StencilArgs&, bool, hipStream_t);        \
+  template hipError_t launch_bcx<N, M_CG1, double, double, double, BC>(const StencilArgs&, bool, hipStream_t);     \
+  template hipError_t launch_bcx<N, M_CG1, float, float, float, BC>(const StencilArgs&, bool, hipStream_t);        \
+  template hipError_t launch_bcx<N, M_CG1, uint16_t, float, float, BC>(const StencilArgs&, bool, hipStream_t);     \
+  template hipError_t launch_bcx<N, M_CGF, float, float, float, BC>(const StencilArgs&, bool, hipStream_t);        \
+  template hipError_t launch_bcx<N, M_CGF, uint16_t, float, float, BC>(const StencilArgs&, bool, hipStream_t);     \
+  template hipError_t launch_bcx<N, M_RESID, double, double, double, BC>(const StencilArgs&, bool, hipStream_t);   \
+  template hipError_t launch_bcx<N, M_RESID, double, double, float, BC>(const StencilArgs&, bool, hipStream_t);    \
   }

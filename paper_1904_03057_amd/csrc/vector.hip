@@ -151,9 +151,28 @@ __global__ __launch_bounds__(256) void add_f32_to_f64_kernel(double* __restrict_
 }
 
 __global__ __launch_bounds__(256) void guess_combine_kernel(double* __restrict__ x, const double* __restrict__ u,
-                                                            const float* __restrict__ du, int64_t n) {
+                                                            const float* __restrict__ du, int64_t n, double scale) {
   const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) x[i] = u[i] + (double)du[i];
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) x[i] = fma(scale, (double)du[i], u[i]);
+}
+
+// Streaming copy with 16-byte accesses, four in flight per thread (the bandwidth reference of the
+// library's kernels); any byte tail is copied by the first block.
+__global__ __launch_bounds__(256) void stream_copy_kernel(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                          int64_t n16, const unsigned char* __restrict__ s8,
+                                                          unsigned char* __restrict__ d8, int64_t nbytes) {
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  for (; i + 3 * stride < n16; i += 4 * stride) {
+    const uint4 a = src[i], b = src[i + stride], c = src[i + 2 * stride], d = src[i + 3 * stride];
+    dst[i] = a;
+    dst[i + stride] = b;
+    dst[i + 2 * stride] = c;
+    dst[i + 3 * stride] = d;
+  }
+  for (; i < n16; i += stride) dst[i] = src[i];
+  if (blockIdx.x == 0)
+    for (int64_t j = n16 * 16 + threadIdx.x; j < nbytes; j += 256) d8[j] = s8[j];
 }
 
 __global__ __launch_bounds__(256) void fill_kernel(uint32_t* __restrict__ x, int64_t nwords) {
@@ -335,8 +354,19 @@ hipError_t launch_add_f32_to_f64(double* x, const float* d, int64_t n, hipStream
   return hipGetLastError();
 }
 
-hipError_t launch_guess_combine(double* x, const double* u, const float* du, int64_t n, hipStream_t st) {
-  hipLaunchKernelGGL(guess_combine_kernel, dim3(vec_blocks(n)), dim3(256), 0, st, x, u, du, n);
+hipError_t launch_guess_combine(double* x, const double* u, const float* du, int64_t n, double scale, hipStream_t st) {
+  hipLaunchKernelGGL(guess_combine_kernel, dim3(vec_blocks(n)), dim3(256), 0, st, x, u, du, n, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_copy(const void* src, void* dst, int64_t nbytes, hipStream_t st) {
+  const int64_t n16 = nbytes / 16;
+  // enough workgroups to keep every CU's memory pipeline full (8 per CU on 256 CUs)
+  int64_t b = (n16 + 255) / 256;
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  hipLaunchKernelGGL(stream_copy_kernel, dim3((unsigned)b), dim3(256), 0, st, (const uint4*)src, (uint4*)dst, n16,
+                     (const unsigned char*)src, (unsigned char*)dst, nbytes);
   return hipGetLastError();
 }
 

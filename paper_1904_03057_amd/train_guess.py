@@ -3,7 +3,8 @@
 Train (dataset from the library's FP64 implicit steps, 2000 Adam steps, batch 4):
     python paper_1904_03057_amd/train_guess.py train --out paper_1904_03057_amd/weights/guess_net_128
         [--grid 128] [--h 1/129] [--tau 1e-4] [--traj 40] [--len 10] [--steps 2000] [--batch 4]
-Evaluate learned vs plain guess (and the coarse-grid guess) over implicit steps (refined FP32 CG to 1e-8):
+Evaluate learned (energy test and residual test) vs plain guess (and the coarse-grid guess) over implicit
+steps (refined FP32 CG to 1e-8):
     python paper_1904_03057_amd/train_guess.py eval --weights paper_1904_03057_amd/weights/guess_net_128
         [--grid 512] [--h 1/513] [--tau 1e-4] [--steps 50]
 
@@ -153,15 +154,18 @@ def cmd_eval(a):
     net.set_weights(w)
     net.set_hparams(out_scale=meta["out_scale"])
     res = {}
-    for name, use in (("plain", False), ("learned", True), ("coarse", False)):
-        # "coarse": the reduced-grid start (halved grid, two-scale prolongation) instead of a network
-        ctx.set_opts(poll_every=2, coarse_guess=1 if name == "coarse" else 0)
+    for name, use in (("plain", False), ("learned", True), ("learned_residual_test", True), ("coarse", False)):
+        # "learned": energy test (A-norm-optimal multiple of the network output); "learned_residual_test":
+        # u^k + du kept if its residual is smaller; "coarse": the reduced-grid start (halved grid,
+        # two-scale prolongation) instead of a network
+        ctx.set_opts(poll_every=2, coarse_guess=1 if name == "coarse" else 0,
+                     guess_test=1 if name == "learned_residual_test" else 0)
         ctx.ensure_workspace(tbs.PREC_MIXED)
         u, q = fields(grid, h, a.seed, torch)
         un = torch.empty_like(u)
         ctx.timestep(u, q, un, tbs.PREC_MIXED, a.rtol, 5000, net if use else None)  # warm-up
         torch.cuda.synchronize()
-        its, used, ratios, times = [], [], [], []
+        its, used, ratios, times, gammas = [], [], [], [], []
         for s in range(a.steps):
             t0 = time.perf_counter()
             st = ctx.timestep(u, q, un, tbs.PREC_MIXED, a.rtol, 5000, net if use else None)
@@ -170,21 +174,26 @@ def cmd_eval(a):
             its.append(st["iters"])
             used.append(st["used_learned_guess"] if name != "coarse" else st["used_coarse_guess"])
             if use:
-                ratios.append(st["rel_res_learned"] / st["rel_res_plain"])
+                gammas.append(st["learned_gamma"])
+                if st["used_learned_guess"]:
+                    ratios.append(st["rel_res_learned"] / st["rel_res_plain"])
             elif name == "coarse":
                 ratios.append(st["rel_res_coarse"] / st["rel_res_plain"])
             u, un = un, u
         res[name] = {"iters_mean": float(np.mean(its)), "iters": its, "s_per_step_mean": float(np.mean(times)),
                      "s_total": float(np.sum(times)), "learned_used": int(np.sum(used)),
-                     "res_ratio_mean": float(np.mean(ratios)) if ratios else None}
+                     "res_ratio_mean": float(np.mean(ratios)) if ratios else None,
+                     "gamma_mean": float(np.mean(gammas)) if gammas else None}
         log("%s: iters %.2f  s/step %.4f  used %d" % (name, res[name]["iters_mean"], res[name]["s_per_step_mean"],
                                                      res[name]["learned_used"]))
     res["coarse"]["coarse_used"] = res["coarse"].pop("learned_used")
     out = {"grid": list(grid), "h": h[0], "tau": tau, "steps": a.steps, "rtol": a.rtol,
            "weights": os.path.basename(a.weights), "trained_on": {k: meta[k] for k in ("grid", "h", "tau")},
-           "plain": res["plain"], "learned": res["learned"], "coarse": res["coarse"],
+           "plain": res["plain"], "learned": res["learned"], "learned_residual_test": res["learned_residual_test"],
+           "coarse": res["coarse"],
            "iters_saved_per_step": res["plain"]["iters_mean"] - res["learned"]["iters_mean"],
            "speedup": res["plain"]["s_per_step_mean"] / res["learned"]["s_per_step_mean"],
+           "iters_saved_per_step_residual_test": res["plain"]["iters_mean"] - res["learned_residual_test"]["iters_mean"],
            "coarse_iters_saved_per_step": res["plain"]["iters_mean"] - res["coarse"]["iters_mean"],
            "coarse_speedup": res["plain"]["s_per_step_mean"] / res["coarse"]["s_per_step_mean"]}
     print(json.dumps(out), flush=True)

@@ -106,7 +106,7 @@ def test_set_opts_validation_without_gpu():
     assert lib.tbs_set_opts(p, ctypes.byref(good)) == tbs.OK
     assert lib.tbs_set_opts(p, None) == tbs.OK
     for field, bad in (("guess_backoff", 2), ("guess_backoff", -1), ("fused_cg", 2), ("inner_rtol", 0.0),
-                       ("coarse_rtol", 1.0), ("poll_every", 0)):
+                       ("coarse_rtol", 1.0), ("poll_every", 0), ("guess_test", 2), ("guess_test", -1)):
         o = tbs.Opts(1e-6, 500, 12, 4, 0, 0, 0, 1, 0, 1e-2, 0)
         setattr(o, field, bad)
         assert lib.tbs_set_opts(p, ctypes.byref(o)) == tbs.E_INVAL, field
@@ -129,4 +129,28 @@ def test_residual_noalloc_validates_before_any_hip_call():
     assert rc == tbs.OK
     assert lib.tbs_residual_noalloc(p, a, b, r, tbs.F64, nrm) == tbs.E_INVAL
     assert b"static buffer" in tbs.lib().tbs_last_error()
+    lib.tbs_destroy(p)
+
+
+def test_setup_robin_validates_without_gpu():
+    lib = tbs.lib()
+    p = ctypes.c_void_p()
+    g = lambda *a: (ctypes.c_int64 * 3)(*a)
+    hh = (ctypes.c_double * 3)(0.1, 0.1, 0.1)
+    # degree 3: every N_d >= 4 floor(n/2) + 2 + n = 9
+    assert lib.tbs_setup_robin(ctypes.byref(p), g(9, 9, 9), 3, hh, 1e-3, 0.01, None) == tbs.OK and p
+    lib.tbs_destroy(p)
+    for args in ((g(8, 9, 9), 3, 0.01), (g(13, 14, 14), 4, 0.01), (g(16, 16, 16), 3, 0.0), (g(16, 16, 16), 3, -1.0),
+                 (g(16, 16, 16), 6, 0.01), (g(16, 16, 16), 3, float("inf"))):
+        p = ctypes.c_void_p()
+        assert lib.tbs_setup_robin(ctypes.byref(p), args[0], args[1], hh, 1e-3, args[2], None) == tbs.E_INVAL
+        assert not p
+    # tbs_setup itself does not take the Robin boundary (it needs gamma)
+    rc, p = _setup(bc=tbs.ROBIN)
+    assert rc == tbs.E_INVAL
+    # the coarse-grid guess is refused on a Robin box
+    p = ctypes.c_void_p()
+    assert lib.tbs_setup_robin(ctypes.byref(p), g(16, 16, 16), 3, hh, 1e-3, 0.01, None) == tbs.OK
+    o = tbs.Opts(1e-6, 500, 12, 4, 0, 0, 0, 1, 1, 1e-2, 0, 0)
+    assert lib.tbs_set_opts(p, ctypes.byref(o)) == tbs.E_INVAL
     lib.tbs_destroy(p)

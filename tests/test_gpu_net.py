@@ -182,6 +182,7 @@ def test_fallback_keeps_plain_path_with_useless_net():
     net.ensure_workspace(grid, 1, False)
     net.set_weights(theta)
     ctx = tbs.Context(grid, n, h, tau, "dirichlet")
+    ctx.set_opts(guess_test=1)
     ctx.ensure_workspace(tbs.PREC_MIXED)
     a, b = dev(np.zeros(grid[::-1])), dev(np.zeros(grid[::-1]))
     s1 = ctx.timestep(dev(u), None, a, tbs.PREC_MIXED, 1e-8, 500, net)
@@ -207,7 +208,7 @@ def test_guess_backoff_skips_a_rejected_net():
     b = dev(np.zeros(grid[::-1]))
     ctx.timestep(u, None, b, tbs.PREC_MIXED, 1e-8, 500, None)
     ref = host(b)
-    ctx.set_opts(guess_backoff=1)
+    ctx.set_opts(guess_backoff=1, guess_test=1)
     ctx.ensure_workspace(tbs.PREC_MIXED)
     skipped = []
     for _ in range(11):
@@ -219,7 +220,7 @@ def test_guess_backoff_skips_a_rejected_net():
         skipped.append(s["skipped_learned_guess"])
     assert skipped == [0, 1, 0, 1, 1, 0, 1, 1, 1, 1, 0]
     # set_opts resets the counters; with backoff off the network runs on every step
-    ctx.set_opts(guess_backoff=0)
+    ctx.set_opts(guess_backoff=0, guess_test=1)
     ctx.ensure_workspace(tbs.PREC_MIXED)
     for _ in range(3):
         s = ctx.timestep(u, None, a, tbs.PREC_MIXED, 1e-8, 500, net)
@@ -253,10 +254,13 @@ def test_adam_over_several_steps_matches_oracle():
 
 
 @pytest.mark.parametrize("prec", ["mixed", "fp64"])
-def test_kept_learned_guess_step_matches_oracle(prec):
+@pytest.mark.parametrize("guess_test", [0, 1])
+def test_kept_learned_guess_step_matches_oracle(prec, guess_test):
     # the trained 128^3 network on a held-out step pair: its guess is kept, and the step that starts
     # from it (guess combine, then refined FP32 or FP64 CG) satisfies the oracle's FP64 residual
-    # test and matches the fast-diagonalisation exact step within kappa * rtol
+    # test and matches the fast-diagonalisation exact step within kappa * rtol.  Energy test: the
+    # multiplier is the oracle's A-norm-optimal gamma = r0.du / du.A du (the device takes r0 in FP32
+    # and A du in FP32 arithmetic), and the guess lowers the A-norm of the error
     import json
     import os
     from oracle import exact
@@ -273,26 +277,93 @@ def test_kept_learned_guess_step_matches_oracle(prec):
     net.set_weights(np.fromfile(os.path.join(wdir, "guess_net_128.f32"), dtype="<f4"))
     net.set_hparams(out_scale=meta["out_scale"])
     ctx = tbs.Context(grid, n, h, tau, "dirichlet")
+    ctx.set_opts(guess_test=guess_test)
     p = tbs.PREC_MIXED if prec == "mixed" else tbs.PREC_FP64
     ctx.ensure_workspace(p)
     tu, tq = dev(u), dev(q)
     un = torch.empty_like(tu)
     st = ctx.timestep(tu, tq, un, p, rtol, 2000, net)
     assert st["converged"] and st["used_learned_guess"] == 1, st
-    # the guess the step used: u + du with the same network forward, residuals as the oracle sees them
+    # the guess the step used: u + gamma du with the same network forward, residuals as the oracle sees them
     du = torch.empty(tu.shape, dtype=torch.float32, device="cuda")
     net.forward(tu, tq, du, False, tau)
-    x0 = u + host(du)
+    d = host(du)
     b = op.rhs(u, q, n, tau, "dirichlet")
     bn = np.linalg.norm(b)
+    r0 = b - op.apply(u, n, h, tau, "dirichlet")
+    if guess_test == 0:
+        ad = op.apply(d, n, h, tau, "dirichlet")
+        gam = float(np.dot(r0.ravel(), d.ravel()) / np.dot(d.ravel(), ad.ravel()))
+        assert abs(st["learned_gamma"] - gam) <= 1e-4 * abs(gam), (st["learned_gamma"], gam)
+        drop = 2 * gam * np.dot(r0.ravel(), d.ravel()) - gam * gam * np.dot(d.ravel(), ad.ravel())
+        assert drop > 0
+    else:
+        assert st["learned_gamma"] == 1.0
+    x0 = u + st["learned_gamma"] * d
     rl = np.linalg.norm(b - op.apply(x0, n, h, tau, "dirichlet")) / bn
-    rp = np.linalg.norm(b - op.apply(u, n, h, tau, "dirichlet")) / bn
+    rp = np.linalg.norm(r0) / bn
     assert abs(st["rel_res_learned"] - rl) <= 1e-9 * rl
     assert abs(st["rel_res_plain"] - rp) <= 1e-9 * rp
-    assert rl < rp
+    xs = exact.solve_dirichlet(b, n, h, tau)
+    if guess_test == 1:
+        assert rl < rp
+    else:  # the A-norm of the error falls by the predicted drop
+        e0, e1 = xs - u, xs - x0
+        ea = lambda e: float(np.dot(e.ravel(), op.apply(e, n, h, tau, "dirichlet").ravel()))
+        assert ea(e1) < ea(e0)
+        assert abs((ea(e0) - ea(e1)) - drop) <= 1e-3 * drop + 1e-12 * ea(e0)
     got = host(un)
     rg = np.linalg.norm(b - op.apply(got, n, h, tau, "dirichlet")) / bn
     assert rg <= rtol * (1 + 1e-6), rg
-    xs = exact.solve_dirichlet(b, n, h, tau)
     kappa = exact.condition_number(grid, n, h, tau, "dirichlet")
     assert np.linalg.norm(got - xs) / np.linalg.norm(xs) <= kappa * rtol
+
+
+def test_energy_test_rejects_a_zero_output_and_keeps_plain_path():
+    # a network whose output is identically zero has no direction to scale (r0.du = du.A du = 0):
+    # the energy test rejects it and the step is the plain path bit for bit
+    grid, n, tau = (32, 24, 20), 3, 1e-3
+    h = tuple(1.0 / (N + 1) for N in grid)
+    u = normal_field(grid[::-1], 3)
+    net = tbs.Net()
+    net.ensure_workspace(grid, 1, False)
+    net.set_weights(np.zeros(cnn.N_PARAMS, dtype=np.float32))
+    ctx = tbs.Context(grid, n, h, tau, "dirichlet")
+    ctx.ensure_workspace(tbs.PREC_MIXED)
+    a, b = dev(np.zeros(grid[::-1])), dev(np.zeros(grid[::-1]))
+    s1 = ctx.timestep(dev(u), None, a, tbs.PREC_MIXED, 1e-8, 500, net)
+    s0 = ctx.timestep(dev(u), None, b, tbs.PREC_MIXED, 1e-8, 500, None)
+    assert s1["used_learned_guess"] == 0 and s1["learned_gamma"] == 0.0
+    assert np.array_equal(host(a), host(b)) and s1["iters"] == s0["iters"]
+    assert s1["rel_res_plain"] == s0["rel_res_plain"]
+
+
+def test_energy_test_scales_a_bad_guess_down_and_never_raises_the_energy_error():
+    # the constant-offset network (rejected outright by the residual test) is kept by the energy
+    # test with its A-norm-optimal multiplier; the A-norm of the guess's error is not above the plain guess's
+    # (oracle check) and the step still converges to the oracle's solution
+    from oracle import exact
+    grid, n, tau = (32, 24, 20), 3, 1e-3
+    h = tuple(1.0 / (N + 1) for N in grid)
+    u = normal_field(grid[::-1], 3)
+    theta = cnn_init(1)
+    theta[cnn.N_PARAMS - 1] = 100.0
+    net = tbs.Net()
+    net.ensure_workspace(grid, 1, False)
+    net.set_weights(theta)
+    ctx = tbs.Context(grid, n, h, tau, "dirichlet")
+    ctx.ensure_workspace(tbs.PREC_MIXED)
+    tu = dev(u)
+    un = torch.empty_like(tu)
+    st = ctx.timestep(tu, None, un, tbs.PREC_MIXED, 1e-10, 2000, net)
+    assert st["converged"] and st["used_learned_guess"] == 1
+    du = torch.empty(tu.shape, dtype=torch.float32, device="cuda")
+    net.forward(tu, None, du, False, tau)
+    d = host(du)
+    assert st["learned_gamma"] != 0.0
+    b = op.rhs(u, None, n, tau, "dirichlet")
+    xs = exact.solve_dirichlet(b, n, h, tau)
+    ea = lambda e: float(np.dot(e.ravel(), op.apply(e, n, h, tau, "dirichlet").ravel()))
+    assert ea(xs - (u + st["learned_gamma"] * d)) <= ea(xs - u)
+    got = host(un)
+    assert np.linalg.norm(b - op.apply(got, n, h, tau, "dirichlet")) <= 1e-10 * (1 + 1e-6) * np.linalg.norm(b)
