@@ -28,6 +28,22 @@ HBM_PEAK_GBS = 8000.0
 WEIGHTS = os.path.join(ROOT, "paper_1904_03057_amd", "weights", "guess_net_928z")
 
 
+# solver variants: (precision, use the network, tbs_opts.guess_backoff, tbs_opts.guess_test)
+SOLVERS = {
+    "learned_backoff": ("mixed", True, 1, 0),    # refined FP32 + learned guess (residual test), backoff
+    "learned_every": ("mixed", True, 0, 0),      # same, network run and judged on every step
+    "learned_energy_backoff": ("mixed", True, 1, 1),  # energy test (A-norm-optimal multiple), backoff
+    "learned_energy_every": ("mixed", True, 0, 1),    # energy test, every step
+    "refined": ("mixed", False, 0, 0),           # refined FP32, plain guess
+    "fp64": ("fp64", False, 0, 0),               # plain FP64 CG
+}
+SOLVER_NAMES = {"learned_backoff": "fp64-refined fp32 CG + learned guess (residual test, backoff)",
+                "learned_every": "fp64-refined fp32 CG + learned guess (residual test, every step)",
+                "learned_energy_backoff": "fp64-refined fp32 CG + learned guess (energy test, backoff)",
+                "learned_energy_every": "fp64-refined fp32 CG + learned guess (energy test, every step)",
+                "refined": "fp64-refined fp32 CG", "fp64": "plain fp64 CG"}
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -40,6 +56,8 @@ def main():
     ap.add_argument("--workload", default="heat928")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed steps (for profiling runs)")
+    ap.add_argument("--solver", default="learned_backoff", choices=list(SOLVERS),
+                    help="solver of the timed steps (the others are timed over the same steps in the extras)")
     ap.add_argument("--probe", default=None,
                     help="run one kernel kind --steps times for counter collection instead of the benchmark: "
                          "apply_f64 | apply_f32 | apply_bf16 | net (network guess) | "
@@ -88,6 +106,13 @@ def main():
         net.set_hparams(out_scale=json.load(open(WEIGHTS + ".json"))["out_scale"])
     torch.cuda.synchronize()
 
+    sprec, suse, sbackoff, stest = SOLVERS[args.solver]
+    if suse and net is None:
+        raise SystemExit("solver %s needs the trained weights %s.f32" % (args.solver, WEIGHTS))
+    PREC = tbs.PREC_MIXED if sprec == "mixed" else tbs.PREC_FP64
+    ctx.set_opts(poll_every=1, guess_backoff=sbackoff, guess_test=stest)
+    ctx.ensure_workspace(PREC)
+
     def step(prec, use_net):
         nonlocal ua, ub
         st = ctx.timestep(ua, None, ub, prec, w.rtol, 5000, net if use_net else None)
@@ -96,9 +121,12 @@ def main():
 
     log("warmup %d" % args.warmup)
     for _ in range(args.warmup):
-        step(tbs.PREC_MIXED, net is not None)
+        step(PREC, suse)
     torch.cuda.synchronize()
     ua.copy_(u0)
+    # the backoff counters restart with the timed steps
+    ctx.set_opts(poll_every=1, guess_backoff=sbackoff, guess_test=stest)
+    ctx.ensure_workspace(PREC)
     torch.cuda.synchronize()
 
     ctx.prof_enable(True)
@@ -110,7 +138,7 @@ def main():
     step_ms = []
     for i in range(args.steps):
         ts = time.perf_counter()
-        stats.append(step(tbs.PREC_MIXED, net is not None))  # synchronises
+        stats.append(step(PREC, suse))  # synchronises
         step_ms.append((time.perf_counter() - ts) * 1e3)
         log("step %d: iters %d sweeps %d rel_res %.3e learned %d" % (
             i, stats[-1]["iters"], stats[-1]["sweeps"], stats[-1]["rel_res_fp64"], stats[-1]["used_learned_guess"]))
@@ -137,15 +165,18 @@ def main():
         "warmup": args.warmup, "ms_per_step": round(ms_total / args.steps, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
         "config": {"workload": w.name, "grid": list(w.grid), "degree": w.degree, "bc": w.bc, "tau": w.tau,
-                   "rtol": w.rtol, "solver": "fp64-refined fp32 CG" + (" + learned guess" if net else ""),
+                   "rtol": w.rtol, "solver": SOLVER_NAMES[args.solver],
                    "global_batch": 1, "parallelism": "none"},
         "wall_s_timed": round(wall, 3),
         "step_ms_host": {"median": round(float(np.median(step_ms)), 3), "min": round(min(step_ms), 3),
                          "max": round(max(step_ms), 3), "first": round(step_ms[0], 3), "last": round(step_ms[-1], 3)},
         "iters_per_step": [s["iters"] for s in stats], "sweeps_per_step": [s["sweeps"] for s in stats],
         "learned_guess_used": [s["used_learned_guess"] for s in stats],
+        "learned_guess_skipped": [s["skipped_learned_guess"] for s in stats],
+        "learned_gamma": [round(s["learned_gamma"], 4) for s in stats],
         "learned_over_plain_residual": [round(s["rel_res_learned"] / s["rel_res_plain"], 4)
-                                        if net is not None and s["rel_res_plain"] > 0 else None for s in stats],
+                                        if suse and s["rel_res_plain"] > 0 and s["rel_res_learned"] == s["rel_res_learned"]
+                                        else None for s in stats],
         "rel_res_fp64": max(s["rel_res_fp64"] for s in stats),
         "roofline": roofline,
         "kernels": {k: {"ms": round(v[0], 3), "GB/s": round(v[1] / (v[0] / 1e3) / 1e9, 1), "launches": v[2]}
@@ -154,6 +185,7 @@ def main():
 
     if not args.no_extras:
         out.update(extras(ctx, tbs, torch, w, u0, stream, net, N, args.steps))
+        out["roofline_varcoef"] = out.get("varcoef", {}).get("roofline")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, params, out.get("all_%d_steps" % args.steps, {}),
                                            out.get("s_per_step", {}))
@@ -284,23 +316,28 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N, k_all):
                     "frac_hbm": round(by / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "ms": round(ms / cnt, 4),
                     "ms_median_of_%d" % reps: round(med, 4), "GDoF/s_median": round(N / (med / 1e3) / 1e9, 1)}
         log("apply %s: %s" % (name, gd[name]))
-    # practical ceiling: a plain device-to-device copy of the FP32 field (read 4 B + write 4 B per DoF)
-    with torch.cuda.stream(stream):
-        for _ in range(2):
-            y32.copy_(u32)
-        c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        c0.record(stream)
-        for _ in range(10):
-            y32.copy_(u32)
-        c1.record(stream)
+    # practical ceiling: the library's 16-byte streaming copy of the FP64 field (read 8 B + write 8 B
+    # per DoF), timed like the applies
+    for _ in range(2):
+        ctx.stream_copy(u0, y64)
     torch.cuda.synchronize()
-    copy_gbs = 8 * N / (c0.elapsed_time(c1) / 10 / 1e3) / 1e9
+    cev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(10)]
+    for a, b in cev:
+        a.record(stream)
+        ctx.stream_copy(u0, y64)
+        b.record(stream)
+    torch.cuda.synchronize()
+    cms = float(np.median([a.elapsed_time(b) for a, b in cev]))
+    copy_gbs = 16 * N / (cms / 1e3) / 1e9
     res["copy_ceiling"] = {"GB/s": round(copy_gbs, 1), "frac_hbm": round(copy_gbs / HBM_PEAK_GBS, 4),
-                           "kernel": "torch copy_ of the FP32 928^3 field"}
+                           "ms_median_of_10": round(cms, 4),
+                           "kernel": "tbs_stream_copy (16-byte accesses) of the FP64 928^3 field"}
     for v in gd.values():
         v["frac_copy"] = round(v["GB/s"] / copy_gbs, 4)
     res["apply"] = gd
     del y64, u32, y32, u16
+    res["varcoef"] = varcoef_apply(tbs, torch, w)
+    res["robin"] = robin_box(tbs, torch, w)
     res["apply_degree_sweep"] = degree_sweep(tbs, torch)
     res["transforms"] = transforms(tbs, torch, w, u0)
     res.update(workload_steps(tbs, torch))
@@ -323,6 +360,8 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N, k_all):
         variants.append(("refined_fp32_learned", tbs.PREC_MIXED, True))
     ctx.ensure_workspace(tbs.PREC_FP64)
     for name, prec, use_net in variants:
+        ctx.set_opts(poll_every=1)
+        ctx.ensure_workspace(tbs.PREC_FP64)
         t, sts = time_steps(prec, use_net, 2)
         sp[name] = {"s_per_step": round(t, 4), "iters": [s["iters"] for s in sts],
                     "rel_res_fp64": max(s["rel_res_fp64"] for s in sts),
@@ -341,23 +380,25 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N, k_all):
         log("%s: %s" % (name, sp[name]))
     ctx.set_opts(poll_every=1)
     res["s_per_step"] = sp
-    # the same k_all steps as the timed run, from the same field: plain FP64 CG, refined FP32 with
-    # the plain guess, and refined FP32 with the network under the backoff policy (a rejected
-    # network is skipped for 1, 2, 4, ... steps before it is tested again)
-    allv = [("plain_fp64_cg", tbs.PREC_FP64, False), ("refined_fp32", tbs.PREC_MIXED, False)]
-    if net is not None:
-        allv.append(("refined_fp32_learned_backoff", tbs.PREC_MIXED, True))
+    # every solver variant over the same k_all steps as the timed run, from the same field
     ra = {}
-    for name, prec, use_net in allv:
-        ctx.set_opts(poll_every=1, guess_backoff=1 if use_net else 0)
-        ctx.ensure_workspace(prec)
+    for key, (prec_s, use_net, backoff, test) in SOLVERS.items():
+        if use_net and net is None:
+            continue
+        prec = tbs.PREC_MIXED if prec_s == "mixed" else tbs.PREC_FP64
+        ctx.set_opts(poll_every=1, guess_backoff=backoff, guess_test=test)
+        ctx.ensure_workspace(tbs.PREC_FP64)
         t, sts = time_steps(prec, use_net, k_all)
-        ra[name] = {"s_per_step": round(t, 4), "steps": k_all, "iters_total": sum(s["iters"] for s in sts),
+        name = {"fp64": "plain_fp64_cg", "refined": "refined_fp32"}.get(key, "refined_fp32_" + key)
+        ra[name] = {"solver": SOLVER_NAMES[key], "s_per_step": round(t, 4), "steps": k_all,
+                    "iters_total": sum(s["iters"] for s in sts),
                     "iters_first_last": [sts[0]["iters"], sts[-1]["iters"]],
                     "rel_res_fp64_max": max(s["rel_res_fp64"] for s in sts)}
         if use_net:
             ra[name]["net_runs"] = sum(1 - s["skipped_learned_guess"] for s in sts)
             ra[name]["net_kept"] = sum(s["used_learned_guess"] for s in sts)
+            ra[name]["gamma_first"] = round(sts[0]["learned_gamma"], 4)
+            ra[name]["iters_first_steps"] = [s["iters"] for s in sts[:5]]
         log("%d steps %s: %s" % (k_all, name, ra[name]))
     ctx.set_opts(poll_every=1)
     ctx.ensure_workspace(tbs.PREC_MIXED)
@@ -375,6 +416,102 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N, k_all):
         log("net forward: %.4f s" % res["net_forward_s"])
         del du
     return res
+
+
+def varcoef_flops_per_dof(n):
+    """Algorithmic flops per coefficient of the sum-factorised variable-coefficient operator: the
+    multiply-adds of the interpolations (z: 4 fields, y: 5, x: 6), the x-, y-, z-projections (4, 3,
+    2) at 2 flops each, and 10 multiplications per Gauss point (weight, mu phi, D grad phi / h^2)."""
+    q, b = (3 * n + 2) // 2, n + 1
+    fma = 4 * q * b + 5 * q * q * b + 6 * q ** 3 * b + 4 * q ** 3 * b + 3 * q * q * b + 2 * q * b
+    return 2 * fma + 10 * q ** 3
+
+
+def varcoef_apply(tbs, torch, w):
+    """Variable-coefficient operator (the operator the paper timed) on the workload's grid, cubic,
+    FP32 and FP64: smooth positive diffusion and absorption fields; ALU roofline (scalar FMA rate,
+    packed FP32 not used: 256 CUs x 64 lanes x 2 flops x 2.4 GHz = 78.6 TFLOP/s for FP32 and FP64)."""
+    N = w.grid[0] * w.grid[1] * w.grid[2]
+    peak = 78.6
+    fl = varcoef_flops_per_dof(w.degree)
+    ctx = tbs.Context(w.grid, w.degree, w.h, w.tau, w.bc)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(17)
+    out = {"flops_per_dof": fl}
+    for dt in ("f32", "f64"):
+        td = torch.float32 if dt == "f32" else torch.float64
+        c = torch.randn(w.grid[::-1], generator=g, device="cuda", dtype=td)
+        d = w.tau * (1.0 + 0.5 * torch.tanh(torch.randn(w.grid[::-1], generator=g, device="cuda", dtype=td)))
+        m = 1.0 + 0.5 * torch.tanh(torch.randn(w.grid[::-1], generator=g, device="cuda", dtype=td))
+        y = torch.empty_like(c)
+        ctx.apply_varcoef(c, d, m, y)
+        torch.cuda.synchronize()
+        ctx.prof_enable(True)
+        reps = 3
+        for _ in range(reps):
+            ctx.apply_varcoef(c, d, m, y)
+        p = ctx.prof_read()
+        ctx.prof_enable(False)
+        ms, by, cnt = p["varcoef_" + dt]
+        t = ms / cnt / 1e3
+        tf = fl * N / t / 1e12
+        out[dt] = {"GDoF/s": round(N / t / 1e9, 3), "ms": round(ms / cnt, 2), "TFLOP/s": round(tf, 2),
+                   "frac_alu": round(tf / peak, 4), "GB/s": round(by / (ms / 1e3) / 1e9, 1)}
+        log("varcoef %s: %s" % (dt, out[dt]))
+        del c, d, m, y
+    out["roofline"] = {"bound": "alu", "achieved": out["f32"]["TFLOP/s"], "peak": peak, "unit": "TFLOP/s",
+                       "frac": out["f32"]["frac_alu"], "traffic": None, "kernel": "varcoef_f32",
+                       "flops_per_dof": fl, "dofs_per_launch": N}
+    out["paper_context"] = ("the paper's on-the-fly cubic operator: 19.1 MDoF/s FP32 at 522^3 on three Radeon "
+                            "Vega Frontier Edition GPUs, 3.7 MDoF/s FP64 on a 24-core EPYC 7401P (Sec. 3)")
+    del ctx
+    return out
+
+
+def robin_box(tbs, torch, w):
+    """Box domain with the Robin / penalty boundary (gamma = 1e-3, the penalty reading of the leg
+    example): apply throughput at the workload's size and the first two implicit steps from the
+    workload's field, refined FP32 and plain FP64."""
+    import workloads
+    N = w.grid[0] * w.grid[1] * w.grid[2]
+    n, gamma = w.degree, 1e-3
+    h = tuple(1.0 / (g - 1 - 2 * (n // 2)) for g in w.grid)
+    ctx = tbs.RobinContext(w.grid, n, h, w.tau, gamma)
+    u = workloads.gaussian_sum(w.grid, w.bc, w.h, workloads.initial_field_gaussians(w), xp=torch, device="cuda",
+                               dtype=torch.float64)
+    out = {"gamma": gamma, "h": h[0]}
+    for dt in ("f64", "f32"):
+        src = u if dt == "f64" else u.float()
+        y = torch.empty_like(src)
+        for _ in range(2):
+            ctx.apply(src, y)
+        torch.cuda.synchronize()
+        ctx.prof_enable(True)
+        for _ in range(10):
+            ctx.apply(src, y)
+        ms, by, cnt = list(ctx.prof_read().values())[0]
+        ctx.prof_enable(False)
+        out["apply_" + dt] = {"GDoF/s": round(N / (ms / cnt / 1e3) / 1e9, 1), "ms": round(ms / cnt, 4),
+                              "frac_hbm": round(by / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del y
+    for name, prec in (("refined_fp32", tbs.PREC_MIXED), ("plain_fp64_cg", tbs.PREC_FP64)):
+        ctx.set_opts(poll_every=1)
+        ctx.ensure_workspace(tbs.PREC_FP64)
+        ua, ub = u.clone(), torch.empty_like(u)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        its, rr = [], []
+        for _ in range(2):
+            st = ctx.timestep(ua, None, ub, prec, w.rtol, 5000)
+            its.append(st["iters"])
+            rr.append(st["rel_res_fp64"])
+            ua, ub = ub, ua
+        torch.cuda.synchronize()
+        out[name] = {"s_per_step": round((time.perf_counter() - t0) / 2, 4), "iters": its, "rel_res_fp64_max": max(rr)}
+        del ua, ub
+    log("robin: %s" % out)
+    del ctx, u
+    return out
 
 
 def degree_sweep(tbs, torch):

@@ -114,13 +114,13 @@ typedef struct {
                               network cost), then test it again; a kept guess resets k.  The
                               counters live in the context; tbs_set_opts resets them. */
   int guess_test;          /* how tbs_timestep judges the network output du (not in the paper):
-                              0 = energy test (default): with r0 = b - A u^k, the guess is
-                              u^k + gamma du, gamma = r0.du / du.A du (the multiple that minimises the
-                              A-norm of the error; one FP32 apply and two dot products), kept if that
-                              A-norm drops, i.e. 2 gamma r0.du - gamma^2 du.A du > 0; for the backoff
-                              a kept guess that does not halve the plain guess's FP64 residual counts
-                              as a rejection.  1 = residual test: u^k + du is kept if its FP64
-                              residual is smaller than that of u^k. */
+                              0 = residual test (default): u^k + du is kept if its FP64 residual is
+                              smaller than that of u^k.  1 = energy test: with r0 = b - A u^k, the
+                              guess is u^k + gamma du, gamma = r0.du / du.A du (the multiple that
+                              minimises the A-norm of the error; one FP32 apply and two dot
+                              products), kept if that A-norm drops, i.e. 2 gamma r0.du - gamma^2
+                              du.A du > 0; for the backoff a kept guess that does not halve the plain
+                              guess's FP64 residual counts as a rejection. */
 } tbs_opts;
 
 /* ---------------------------------------------------------------- context ---------------- */

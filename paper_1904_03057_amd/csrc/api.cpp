@@ -1003,7 +1003,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     rc = tbs_net_guess_internal(g, grid, c->bc == TBS_BC_PERIODIC, c->tau, c->st, u_prev, q, &du);
     if (rc) return rc;
     const bool refined = (prec == TBS_PREC_MIXED || prec == TBS_PREC_MIXED_BF16);
-    if (c->opts.guess_test == 0) {
+    if (c->opts.guess_test == 1) {
       // energy test: r0 = b - A u^k (FP64 kernel, kept as FP32 in the first sweep's residual array),
       // A du in FP32, gamma = r0.du / du.A du minimises ||x* - (u^k + gamma du)||_A, and the A-norm of
       // the error drops by 2 gamma r0.du - gamma^2 du.A du (= (r0.du)^2 / du.A du)
@@ -1230,7 +1230,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     // backoff bookkeeping: a rejected guess counts, and so (energy test) does a kept one that did not
     // halve the plain guess's residual: it cannot save the iterations its network costs
     const bool paid = st.used_learned_guess &&
-                      (c->opts.guess_test != 0 || st.rel_res_learned <= 0.5 * st.rel_res_plain);
+                      (c->opts.guess_test == 0 || st.rel_res_learned <= 0.5 * st.rel_res_plain);
     if (paid) {
       c->guess_rejects = 0;
     } else {

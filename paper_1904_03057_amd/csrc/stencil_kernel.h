@@ -40,7 +40,7 @@ template <typename Ts, typename Tc> __device__ __forceinline__ Ts from_c(Tc v) {
 template <> __device__ __forceinline__ uint16_t from_c<uint16_t, float>(float v) { return f32_to_bf16(v); }
 
 template <int N, int TY, int MODE, typename Tin, typename Tc, typename Tout, int BC, bool VEC, int WX>
-__global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
+__global__ __launch_bounds__(256 * WX) __attribute__((amdgpu_waves_per_eu(BC == BC_ROBIN ? 2 : 1))) void stencil_kernel(StencilArgs a) {
   constexpr int NT = 256 * WX;                     // threads: WX column groups of 64 x 4 waves
   constexpr int VE = VEC ? 16 / (int)sizeof(Tin) : 1;
   using Raw = VecN<Tin, VE>;   // staged input (u, u_prev, x, p_old)
@@ -75,6 +75,7 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
   // BC_ROBIN: corner blocks in compute precision (cm, cvx, cwy, cwz, each kRobinMaxZ^2)
   constexpr int RBT = kRobinMaxZ * kRobinMaxZ;
   __shared__ Tc rbt[BC == BC_ROBIN ? 4 * RBT : 1];
+  __shared__ Tc zl[BC == BC_ROBIN ? (2 * (N / 2) + 1) * TY * TX : 1];
 
   if (CG && a.scal->done) return;
 
@@ -289,13 +290,15 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
   for (int s = 0; s < T; ++s)
 #pragma unroll
     for (int i = 0; i < RPW; ++i) acc[s][i] = (Tc)0;
-  // BC_ROBIN: z-corner contributions to the output planes j-th from an end, j < ZM
+  // BC_ROBIN: z-corner contributions to the output planes j-th from an end, j < ZM, kept in LDS
+  // (each thread only touches its own column and rows)
   constexpr int ZM = BC == BC_ROBIN ? 2 * (N / 2) + 1 : 1;
-  Tc zacc[ZM][RPW];
+  if constexpr (BC == BC_ROBIN) {
 #pragma unroll
-  for (int j = 0; j < ZM; ++j)
+    for (int j = 0; j < ZM; ++j)
 #pragma unroll
-    for (int i = 0; i < RPW; ++i) zacc[j][i] = (Tc)0;
+      for (int i = 0; i < RPW; ++i) zl[(j * TY + wave * RPW + i) * TX + col] = (Tc)0;
+  }
 
   const int gxo = x0 + col;
   const bool colown = gxo < nx;
@@ -422,8 +425,10 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
               const int ri = k < ZM ? k : nz - 1 - k;
 #pragma unroll
               for (int j = 0; j < ZM; ++j) {
-                zacc[j][i] = fmad(rbt[j * kRobinMaxZ + ri], MODE == M_RHS ? P : Rr, zacc[j][i]);
-                if (MODE != M_RHS) zacc[j][i] = fmad(rbt[3 * RBT + j * kRobinMaxZ + ri], P, zacc[j][i]);
+                Tc* zp = zl + (j * TY + wave * RPW + i) * TX + col;
+                Tc zv = fmad(rbt[j * kRobinMaxZ + ri], MODE == M_RHS ? P : Rr, *zp);
+                if (MODE != M_RHS) zv = fmad(rbt[3 * RBT + j * kRobinMaxZ + ri], P, zv);
+                *zp = zv;
               }
             }
           }
@@ -439,12 +444,10 @@ __global__ __launch_bounds__(256 * WX) void stencil_kernel(StencilArgs a) {
 #pragma unroll
           for (int i = 0; i < RPW; ++i) {
             zadd[i] = (Tc)0;
-#pragma unroll
-            for (int j = 0; j < ZM; ++j) {
-              if (j == zj) {
-                zadd[i] = zacc[j][i];
-                zacc[j][i] = (Tc)0;
-              }
+            if (zj >= 0) {
+              Tc* zp = zl + (zj * TY + wave * RPW + i) * TX + col;
+              zadd[i] = *zp;
+              *zp = (Tc)0;
             }
           }
         }

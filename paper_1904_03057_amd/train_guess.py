@@ -3,7 +3,7 @@
 Train (dataset from the library's FP64 implicit steps, 2000 Adam steps, batch 4):
     python paper_1904_03057_amd/train_guess.py train --out paper_1904_03057_amd/weights/guess_net_128
         [--grid 128] [--h 1/129] [--tau 1e-4] [--traj 40] [--len 10] [--steps 2000] [--batch 4]
-Evaluate learned (energy test and residual test) vs plain guess (and the coarse-grid guess) over implicit
+Evaluate learned (residual test and energy test) vs plain guess (and the coarse-grid guess) over implicit
 steps (refined FP32 CG to 1e-8):
     python paper_1904_03057_amd/train_guess.py eval --weights paper_1904_03057_amd/weights/guess_net_128
         [--grid 512] [--h 1/513] [--tau 1e-4] [--steps 50]
@@ -154,12 +154,12 @@ def cmd_eval(a):
     net.set_weights(w)
     net.set_hparams(out_scale=meta["out_scale"])
     res = {}
-    for name, use in (("plain", False), ("learned", True), ("learned_residual_test", True), ("coarse", False)):
-        # "learned": energy test (A-norm-optimal multiple of the network output); "learned_residual_test":
-        # u^k + du kept if its residual is smaller; "coarse": the reduced-grid start (halved grid,
-        # two-scale prolongation) instead of a network
+    for name, use in (("plain", False), ("learned", True), ("learned_energy_test", True), ("coarse", False)):
+        # "learned": u^k + du kept if its residual is smaller; "learned_energy_test": the A-norm-optimal
+        # multiple of the network output; "coarse": the reduced-grid start (halved grid, two-scale
+        # prolongation) instead of a network
         ctx.set_opts(poll_every=2, coarse_guess=1 if name == "coarse" else 0,
-                     guess_test=1 if name == "learned_residual_test" else 0)
+                     guess_test=1 if name == "learned_energy_test" else 0)
         ctx.ensure_workspace(tbs.PREC_MIXED)
         u, q = fields(grid, h, a.seed, torch)
         un = torch.empty_like(u)
@@ -189,11 +189,11 @@ def cmd_eval(a):
     res["coarse"]["coarse_used"] = res["coarse"].pop("learned_used")
     out = {"grid": list(grid), "h": h[0], "tau": tau, "steps": a.steps, "rtol": a.rtol,
            "weights": os.path.basename(a.weights), "trained_on": {k: meta[k] for k in ("grid", "h", "tau")},
-           "plain": res["plain"], "learned": res["learned"], "learned_residual_test": res["learned_residual_test"],
+           "plain": res["plain"], "learned": res["learned"], "learned_energy_test": res["learned_energy_test"],
            "coarse": res["coarse"],
            "iters_saved_per_step": res["plain"]["iters_mean"] - res["learned"]["iters_mean"],
            "speedup": res["plain"]["s_per_step_mean"] / res["learned"]["s_per_step_mean"],
-           "iters_saved_per_step_residual_test": res["plain"]["iters_mean"] - res["learned_residual_test"]["iters_mean"],
+           "iters_saved_per_step_energy_test": res["plain"]["iters_mean"] - res["learned_energy_test"]["iters_mean"],
            "coarse_iters_saved_per_step": res["plain"]["iters_mean"] - res["coarse"]["iters_mean"],
            "coarse_speedup": res["plain"]["s_per_step_mean"] / res["coarse"]["s_per_step_mean"]}
     print(json.dumps(out), flush=True)

@@ -182,7 +182,6 @@ def test_fallback_keeps_plain_path_with_useless_net():
     net.ensure_workspace(grid, 1, False)
     net.set_weights(theta)
     ctx = tbs.Context(grid, n, h, tau, "dirichlet")
-    ctx.set_opts(guess_test=1)
     ctx.ensure_workspace(tbs.PREC_MIXED)
     a, b = dev(np.zeros(grid[::-1])), dev(np.zeros(grid[::-1]))
     s1 = ctx.timestep(dev(u), None, a, tbs.PREC_MIXED, 1e-8, 500, net)
@@ -208,7 +207,7 @@ def test_guess_backoff_skips_a_rejected_net():
     b = dev(np.zeros(grid[::-1]))
     ctx.timestep(u, None, b, tbs.PREC_MIXED, 1e-8, 500, None)
     ref = host(b)
-    ctx.set_opts(guess_backoff=1, guess_test=1)
+    ctx.set_opts(guess_backoff=1)
     ctx.ensure_workspace(tbs.PREC_MIXED)
     skipped = []
     for _ in range(11):
@@ -220,7 +219,7 @@ def test_guess_backoff_skips_a_rejected_net():
         skipped.append(s["skipped_learned_guess"])
     assert skipped == [0, 1, 0, 1, 1, 0, 1, 1, 1, 1, 0]
     # set_opts resets the counters; with backoff off the network runs on every step
-    ctx.set_opts(guess_backoff=0, guess_test=1)
+    ctx.set_opts(guess_backoff=0)
     ctx.ensure_workspace(tbs.PREC_MIXED)
     for _ in range(3):
         s = ctx.timestep(u, None, a, tbs.PREC_MIXED, 1e-8, 500, net)
@@ -291,7 +290,7 @@ def test_kept_learned_guess_step_matches_oracle(prec, guess_test):
     b = op.rhs(u, q, n, tau, "dirichlet")
     bn = np.linalg.norm(b)
     r0 = b - op.apply(u, n, h, tau, "dirichlet")
-    if guess_test == 0:
+    if guess_test == 1:
         ad = op.apply(d, n, h, tau, "dirichlet")
         gam = float(np.dot(r0.ravel(), d.ravel()) / np.dot(d.ravel(), ad.ravel()))
         assert abs(st["learned_gamma"] - gam) <= 1e-4 * abs(gam), (st["learned_gamma"], gam)
@@ -305,7 +304,7 @@ def test_kept_learned_guess_step_matches_oracle(prec, guess_test):
     assert abs(st["rel_res_learned"] - rl) <= 1e-9 * rl
     assert abs(st["rel_res_plain"] - rp) <= 1e-9 * rp
     xs = exact.solve_dirichlet(b, n, h, tau)
-    if guess_test == 1:
+    if guess_test == 0:
         assert rl < rp
     else:  # the A-norm of the error falls by the predicted drop
         e0, e1 = xs - u, xs - x0
@@ -329,6 +328,7 @@ def test_energy_test_rejects_a_zero_output_and_keeps_plain_path():
     net.ensure_workspace(grid, 1, False)
     net.set_weights(np.zeros(cnn.N_PARAMS, dtype=np.float32))
     ctx = tbs.Context(grid, n, h, tau, "dirichlet")
+    ctx.set_opts(guess_test=1)
     ctx.ensure_workspace(tbs.PREC_MIXED)
     a, b = dev(np.zeros(grid[::-1])), dev(np.zeros(grid[::-1]))
     s1 = ctx.timestep(dev(u), None, a, tbs.PREC_MIXED, 1e-8, 500, net)
@@ -352,6 +352,7 @@ def test_energy_test_scales_a_bad_guess_down_and_never_raises_the_energy_error()
     net.ensure_workspace(grid, 1, False)
     net.set_weights(theta)
     ctx = tbs.Context(grid, n, h, tau, "dirichlet")
+    ctx.set_opts(guess_test=1)
     ctx.ensure_workspace(tbs.PREC_MIXED)
     tu = dev(u)
     un = torch.empty_like(tu)
