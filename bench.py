@@ -61,7 +61,8 @@ def main():
     ap.add_argument("--probe", default=None,
                     help="run one kernel kind --steps times for counter collection instead of the benchmark: "
                          "apply_f64 | apply_f32 | apply_bf16 | net (network guess) | "
-                         "copy (f64->f32 conversion, the traffic calibration)")
+                         "copy (f64->f32 conversion, the traffic calibration) | copy16 (16-byte streaming copy) | "
+                         "varcoef_f32 | varcoef_f64 | robin_f32 | robin_f64")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the library has no multi-GPU path (the design notes "
@@ -268,6 +269,26 @@ def probe(args):
         dst = torch.empty(u.shape, dtype=torch.float32, device="cuda")
         run = lambda: ctx.convert(u, dst)
         nbytes = 12 * N
+    elif kind == "copy16":
+        dst = torch.empty_like(u)
+        run = lambda: ctx.stream_copy(u, dst)
+        nbytes = 16 * N
+    elif kind in ("varcoef_f32", "varcoef_f64"):
+        td = torch.float32 if kind.endswith("f32") else torch.float64
+        src = u.to(td)
+        d = torch.full_like(src, w.tau) * (1.0 + 0.5 * torch.tanh(src))
+        m = 1.0 + 0.5 * torch.tanh(src)
+        dst = torch.empty_like(src)
+        run = lambda: ctx.apply_varcoef(src, d, m, dst)
+        nbytes = 4 * src.element_size() * N
+    elif kind in ("robin_f32", "robin_f64"):
+        n = w.degree
+        rctx = tbs.RobinContext(w.grid, n, tuple(1.0 / (g - 1 - 2 * (n // 2)) for g in w.grid), w.tau, 1e-3)
+        ctx = rctx
+        src = u if kind.endswith("f64") else u.to(torch.float32)
+        dst = torch.empty_like(src)
+        run = lambda: rctx.apply(src, dst)
+        nbytes = 2 * src.element_size() * N
     else:
         raise SystemExit("unknown probe " + kind)
     for _ in range(2):  # warm-up (code-object load, caches)
