@@ -300,6 +300,7 @@ extern "C" int tbs_setup(tbs_ctx** out, const int64_t grid[3], int degree, const
   c->opts.fused_cg = 1;
   c->opts.coarse_guess = 0;
   c->opts.coarse_rtol = 1e-2;
+  c->opts.persistent = 0;
   *out = c;
   return TBS_OK;
 }
@@ -456,12 +457,13 @@ extern "C" int tbs_set_opts(tbs_ctx* c, const tbs_opts* o) {
     c->opts.inner_rtol = 1e-6; c->opts.inner_max_iter = 500; c->opts.max_sweeps = 12; c->opts.poll_every = 4;
     c->opts.zchunk = 0; c->opts.tile_order = 0; c->opts.nt_store = 0; c->opts.fused_cg = 1;
     c->opts.coarse_guess = 0; c->opts.coarse_rtol = 1e-2; c->opts.guess_backoff = 0; c->opts.guess_test = 0;
+    c->opts.persistent = 0;
   } else {
     if (!(o->inner_rtol > 0 && o->inner_rtol < 1) || o->inner_max_iter < 1 || o->max_sweeps < 1 ||
         o->poll_every < 1 || o->zchunk < 0 || o->tile_order < 0 || o->tile_order > 1 || o->nt_store < 0 ||
         o->nt_store > 1 || o->fused_cg < 0 || o->fused_cg > 1 || o->coarse_guess < 0 || o->coarse_guess > 1 ||
         !(o->coarse_rtol > 0 && o->coarse_rtol < 1) || o->guess_backoff < 0 || o->guess_backoff > 1 ||
-        o->guess_test < 0 || o->guess_test > 1)
+        o->guess_test < 0 || o->guess_test > 1 || o->persistent < 0)
       return set_err(TBS_E_INVAL, "bad options");
     if (o->coarse_guess) {
       if (c->transform_degree) return set_err(TBS_E_INVAL, "coarse guess on a transform context");
@@ -754,13 +756,14 @@ static int cg1_async(tbs_ctx* c, const CgArrays& A, int dt, int k) {
   a.io0 = A.x;
   a.scal = scal(c, SC_CG);
   a.first = (k == 0);
+  a.persist = c->opts.persistent;
   const double tc = dt == 0 ? 8 : 4, tp = dt == 0 ? 8 : (dt == 1 ? 4 : 2);
   // first iteration: read r, write p and q; later: read r, p_old, x, write p, q, x
   const double b1 = (double)c->N * (k == 0 ? (2 * tc + tp) : (4 * tc + 2 * tp));
   int ps = prof_begin(c, 5 + dt, k, b1);
   HIPCHK(launch_cg1(a, c->n, c->bc, dt, c->st));
   prof_end(c, ps);
-  HIPCHK(launch_finalize(FIN_ALPHA, part0(c), nullptr, stencil_blocks(a, M_CG1, dt == 0 ? 8 : 4), scal(c, SC_CG),
+  HIPCHK(launch_finalize(FIN_ALPHA, part0(c), nullptr, stencil_last_blocks(), scal(c, SC_CG),
                          0.0, c->st));
   ps = prof_begin(c, dt == 0 ? 9 : 10, k, (double)c->N * 3 * tc);
   HIPCHK(launch_cg2(A.r, A.q, c->N, dt == 0 ? 0 : 1, part0(c), scal(c, SC_CG), c->st));
@@ -786,13 +789,14 @@ static int cgf_async(tbs_ctx* c, const CgArrays& A, int dt, int k) {
   a.io0 = A.x;
   a.scal = scal(c, SC_CG);
   a.first = (k == 0);
+  a.persist = c->opts.persistent;
   const double tp = dt == 1 ? 4 : 2;
   // first iteration: read r, write r, p, q; later: read r, q, p_old, x, write r, p, q, x
   const double b1 = (double)c->N * (k == 0 ? (12 + tp) : (2 * (12 + tp)));
   int ps = prof_begin(c, dt == 1 ? 11 : 12, k, b1);
   HIPCHK(launch_cgf(a, c->n, c->bc, dt, c->st));
   prof_end(c, ps);
-  HIPCHK(launch_finalize(FIN_FUSED, part0(c), part1(c), stencil_blocks(a, M_CGF, 4), scal(c, SC_CG), 0.0, c->st,
+  HIPCHK(launch_finalize(FIN_FUSED, part0(c), part1(c), stencil_last_blocks(), scal(c, SC_CG), 0.0, c->st,
                          part2(c), part3(c)));
   return TBS_OK;
 }

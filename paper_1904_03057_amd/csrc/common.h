@@ -68,6 +68,7 @@ struct StencilArgs {
   int order;                   // tile order: 0 x-tiles fastest, 1 y-tiles fastest
   int nt_store;                // 1: outputs written with non-temporal stores
   RobinCorner rb;              // BC_ROBIN corner blocks
+  int persist;                 // 0: one workgroup per tile; 1: only as many as are resident; n > 1: at most n
 };
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }

@@ -41,6 +41,13 @@ constexpr int stencil_tile_y(int mode, int compute_bytes) {
 template <int N, int MODE, typename Tin, typename Tc, typename Tout, int BC>
 hipError_t launch_bcx(const StencilArgs& a, bool vec, hipStream_t st);
 
+// Workgroups (= partial sums written) of the last stencil launch on this thread: the tile count,
+// or the resident-workgroup count of a persistent launch.
+extern thread_local int g_stencil_blocks;
+inline int stencil_last_blocks() { return g_stencil_blocks; }
+// Workgroups of `kernel` (block threads each) the whole GPU holds at once (0 if unknown).
+int resident_blocks(const void* kernel, int block);
+
 template <int N, int MODE, typename Tin, typename Tc, typename Tout>
 inline hipError_t launch_bc(const StencilArgs& a, int bc, bool vec, hipStream_t st) {
   if (bc == BC_PERIODIC) return launch_bcx<N, MODE, Tin, Tc, Tout, BC_PERIODIC>(a, vec, st);

@@ -98,7 +98,13 @@ __global__ __launch_bounds__(256 * WX) __attribute__((amdgpu_waves_per_eu(BC == 
   const int col = (wv % WX) * 64 + lane;           // tile column of this lane
   const int wave = wv / WX;                        // row group 0..3
 
-  const int bid = xcd_remap(blockIdx.x, a.nblocks);
+  // persistent launches (grid smaller than the tile count) walk the tiles in rounds of gridDim.x:
+  // the blocks of one round start together and march the same z-planes in step, so the halo rows
+  // and columns their neighbours fetch are still in L2; a plain launch has one round
+  double part0 = 0.0, part1 = 0.0, part2 = 0.0, part3 = 0.0;
+  for (int tile = blockIdx.x; tile < a.nblocks; tile += gridDim.x) {
+  const int r0 = tile - (int)blockIdx.x;  // first tile of this round
+  const int bid = r0 + xcd_remap(blockIdx.x, min((int)gridDim.x, a.nblocks - r0));
   // logical tile order (x- or y-tiles fastest, then the other, then z-chunks): the tiles an XCD
   // runs at the same time are neighbours whose halo cache lines meet in that XCD's L2
   int txi, tyi, czi;
@@ -192,7 +198,6 @@ __global__ __launch_bounds__(256 * WX) __attribute__((amdgpu_waves_per_eu(BC == 
   RawC px[PF][NVC];
   RawC pq[FUSED ? PF : 1][FUSED ? NV : 1];  // CGF: q_old
   int pk[PF] = {};  // plane index held in each prefetch slot
-  double part0 = 0.0, part1 = 0.0, part2 = 0.0, part3 = 0.0;
 
   auto fetch = [&](int k, const int sl) {
     bool pvalid = true;
@@ -490,6 +495,8 @@ __global__ __launch_bounds__(256 * WX) __attribute__((amdgpu_waves_per_eu(BC == 
       }
     }
   }
+  __syncthreads();  // the next tile restages the LDS buffers the last outputs of this one read
+  }
 
   if (CG || MODE == M_RESID) {
     part0 = wave_sum(part0);
@@ -532,11 +539,24 @@ hipError_t launch_bcx(const StencilArgs& a0, bool vec, hipStream_t st) {
   a.tiles_x = (a.nx + 64 * WX - 1) / (64 * WX);
   a.tiles_y = (a.ny + TY - 1) / TY;
   a.nblocks = a.tiles_x * a.tiles_y * a.nchunks;
-  dim3 grid(a.nblocks), block(256 * WX);
+  auto kv = stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC, true, WX>;
+  auto ks = stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC, false, WX>;
+  int blocks = a.nblocks;
+  if (a.persist == 1) {
+    // as many workgroups as the GPU holds at once (queried once per kernel instance)
+    static const int resident[2] = {resident_blocks((const void*)ks, 256 * WX),
+                                    resident_blocks((const void*)kv, 256 * WX)};
+    const int r = resident[vec ? 1 : 0];
+    if (r > 0 && r < blocks) blocks = r;
+  } else if (a.persist > 1 && a.persist < blocks) {
+    blocks = a.persist;  // an explicit cap
+  }
+  g_stencil_blocks = blocks;
+  dim3 grid(blocks), block(256 * WX);
   if (vec)
-    hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC, true, WX>), grid, block, 0, st, a);
+    hipLaunchKernelGGL(kv, grid, block, 0, st, a);
   else
-    hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC, false, WX>), grid, block, 0, st, a);
+    hipLaunchKernelGGL(ks, grid, block, 0, st, a);
   return hipGetLastError();
 }
 
