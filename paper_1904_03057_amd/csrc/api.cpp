@@ -246,6 +246,7 @@ static double* part3(const tbs_ctx* c) { return (double*)(c->ws + 1024 + 3 * ali
 
 static StencilArgs base_args(const tbs_ctx* c) {
   StencilArgs a{};
+  a.rscale = 1.0;
   a.nx = (int)c->nx; a.ny = (int)c->ny; a.nz = (int)c->nz; a.zc = c->zc;
   a.tiles_x = c->tiles_x; a.tiles_y = c->tiles_y; a.nchunks = c->nchunks; a.nblocks = c->nblocks;
   a.t = c->taps;
@@ -600,10 +601,11 @@ extern "C" int tbs_apply_varcoef(tbs_ctx* c, const void* u, const void* d, const
   return TBS_OK;
 }
 
-// r = b - A x (FP64), norms to scal slot; r written if r != NULL (r_dt F64/F32)
+// r = (b - A x) rscale (FP64), its norms to scal slot; r written if r != NULL (r_dt F64/F32)
 static int resid_async(tbs_ctx* c, const double* x, const double* b, void* r, int r_dt, int slot, int fin_op,
-                       double rtol) {
+                       double rtol, double rscale = 1.0) {
   StencilArgs a = base_args(c);
+  a.rscale = rscale;
   a.in0 = x;
   a.bvec = b;
   a.out0 = r;
@@ -1187,6 +1189,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     int total = 0, sweeps = 0;
     for (;;) {
       Scalars s;
+      double rscale = 1.0;  // the stored FP32 residual is r * rscale; the correction is scaled back
       if (sweeps == 0 && have_res0) {
         s = res0;  // r32 and the residual partial sums of u_next = u_prev are already in place
       } else {
@@ -1194,6 +1197,18 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
         if (rc) return rc;
         rc = read_scal(c, SC_AUX, &s);
         if (rc) return rc;
+      }
+      {
+        // the inner FP32 solve sees r / s (the refinement's scaling, a power of two near the RMS of
+        // r) whenever r's elements would leave the normal FP32 range: redo the residual scaled
+        const double rms = std::sqrt(s.out / (double)c->N);
+        if (rms > 0.0 && std::isfinite(rms) && (rms < 0x1p-96 || rms > 0x1p96)) {
+          rscale = std::ldexp(1.0, -std::ilogb(rms));
+          rc = resid_async(c, have_x ? u_next : u_prev, b64, r32, TBS_F32, SC_AUX, FIN_NORMS, 0.0, rscale);
+          if (rc) return rc;
+          rc = read_scal(c, SC_AUX, &s);
+          if (rc) return rc;
+        }
       }
       const double rel = s.out2 > 0 ? std::sqrt(s.out / s.out2) : std::sqrt(s.out);
       if (sweeps == 0) {
@@ -1220,7 +1235,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
       if (irc == TBS_E_BREAKDOWN && nit == 0) { result = irc; break; }
       if (irc < 0 && irc != TBS_E_BREAKDOWN) return irc;
       HIPCHK(launch_refine_add(u_next, have_x ? u_next : u_prev, d32, A.p[0], A.p[1], c->N, dt, scal(c, SC_CG),
-                               c->st));
+                               1.0 / rscale, c->st));
       HIPCHK(launch_finalize(FIN_CLEAR_PENDING, nullptr, nullptr, 0, scal(c, SC_CG), 0.0, c->st));
       have_x = true;
       ++sweeps;

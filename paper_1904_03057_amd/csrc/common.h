@@ -69,6 +69,7 @@ struct StencilArgs {
   int nt_store;                // 1: outputs written with non-temporal stores
   RobinCorner rb;              // BC_ROBIN corner blocks
   int persist;                 // 0: one workgroup per tile; 1: only as many as are resident; n > 1: at most n
+  double rscale;               // RESID: factor (a power of two) on the stored residual and its sums
 };
 
 __device__ __forceinline__ float bf16_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }

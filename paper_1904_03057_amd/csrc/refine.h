@@ -4,10 +4,10 @@
 
 namespace tbs {
 
-// out = base + (double)(d + alpha p_{nit-1}) with the inner solve's pending update applied in FP32
-// exactly as the CG flush would apply it to d (alpha, nit and the pending flag are read from s on
-// the device); p_{nit-1} = (nit odd ? p1 : p0), dt 1 (FP32 p) or 2 (bf16 p).  out may equal base.
+// out = base + scale (double)(d + alpha p_{nit-1}) with the inner solve's pending update applied in
+// FP32 exactly as the CG flush would apply it to d (alpha, nit and the pending flag are read from s
+// on the device); p_{nit-1} = (nit odd ? p1 : p0), dt 1 (FP32 p) or 2 (bf16 p).  out may equal base.
 hipError_t launch_refine_add(double* out, const double* base, const float* d, const void* p0, const void* p1,
-                             int64_t n, int dt, const Scalars* s, hipStream_t st);
+                             int64_t n, int dt, const Scalars* s, double scale, hipStream_t st);
 
 }  // namespace tbs

@@ -480,8 +480,10 @@ __global__ __launch_bounds__(256 * WX) __attribute__((amdgpu_waves_per_eu(BC == 
                   part2 = fma(qv, qv, part2);
                 }
               } else {
-                const double b = a.bvec[gi];
-                const double r = b - (double)val;
+                // rscale (a power of two, 1 unless the refinement keeps r inside FP32 range) scales
+                // the stored residual and both sums alike: their ratio is unchanged
+                const double b = a.bvec[gi] * a.rscale;
+                const double r = b - (double)val * a.rscale;
                 if (a.out0) Io<Tout>::template st<double>(a.out0, gi, r);
                 part0 = fma(r, r, part0);
                 part1 = fma(b, b, part1);

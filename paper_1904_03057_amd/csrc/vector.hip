@@ -105,11 +105,11 @@ __global__ __launch_bounds__(256) void flush_kernel(T* __restrict__ x, const Tp*
     x[i] += alpha * Io<Tp>::template ld<T>(p, i);
 }
 
-// out = base + (d + alpha p), the FP32 part formed exactly as flush_kernel forms x + alpha p
+// out = base + scale (d + alpha p), the FP32 part formed exactly as flush_kernel forms x + alpha p
 template <typename Tp>
 __global__ __launch_bounds__(256) void refine_add_kernel(double* out, const double* base, const float* __restrict__ d,
                                                          const Tp* __restrict__ p0, const Tp* __restrict__ p1,
-                                                         int64_t n, const Scalars* s) {
+                                                         int64_t n, const Scalars* s, double scale) {
   const bool pending = s->pending != 0;
   const float alpha = (float)s->alpha;
   const Tp* p = (s->nit & 1) ? p1 : p0;
@@ -117,7 +117,7 @@ __global__ __launch_bounds__(256) void refine_add_kernel(double* out, const doub
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
     float x = d[i];
     if (pending) x += alpha * Io<Tp>::template ld<float>(p, i);
-    out[i] = base[i] + (double)x;
+    out[i] = fma(scale, (double)x, base[i]);
   }
 }
 
@@ -316,14 +316,14 @@ hipError_t launch_flush(void* x, const void* p0, const void* p1, int64_t n, int 
 }
 
 hipError_t launch_refine_add(double* out, const double* base, const float* d, const void* p0, const void* p1,
-                             int64_t n, int dt, const Scalars* s, hipStream_t st) {
+                             int64_t n, int dt, const Scalars* s, double scale, hipStream_t st) {
   const int b = vec_blocks(n);
   if (dt == 1)
     hipLaunchKernelGGL(refine_add_kernel<float>, dim3(b), dim3(256), 0, st, out, base, d, (const float*)p0,
-                       (const float*)p1, n, s);
+                       (const float*)p1, n, s, scale);
   else
     hipLaunchKernelGGL(refine_add_kernel<uint16_t>, dim3(b), dim3(256), 0, st, out, base, d, (const uint16_t*)p0,
-                       (const uint16_t*)p1, n, s);
+                       (const uint16_t*)p1, n, s, scale);
   return hipGetLastError();
 }
 

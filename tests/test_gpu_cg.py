@@ -266,3 +266,23 @@ def test_timestep_output_independent_of_prior_contents(prec, coarse):
     assert sc["iters"] == 0 and np.all(np.isfinite(host(c)))
     if not sc["used_coarse_guess"]:
         assert np.array_equal(host(c), host(u))
+
+
+@pytest.mark.parametrize("mag", [1e-36, 3e37])
+def test_refinement_keeps_the_inner_residual_in_fp32_range(mag):
+    # the refinement solves A d = r / s (s a power of two near the residual's RMS) whenever r's
+    # elements would leave the normal FP32 range, and adds s d back in FP64: fields at 1e-36 and
+    # 3e37 reach the oracle's exact step as fields of size one do
+    grid, n, tau, rtol = (40, 24, 20), 3, 1e-3, 1e-10
+    h = tuple(1.0 / (N + 1) for N in grid)
+    u = op.mass_apply(normal_field(grid[::-1], 14), n, "dirichlet") * mag
+    ctx = _ctx(grid, n, h, tau, "dirichlet", tbs.PREC_MIXED)
+    un = dev(np.zeros(grid[::-1]))
+    st = ctx.timestep(dev(u), None, un, tbs.PREC_MIXED, rtol, 2000)
+    assert st["converged"], st
+    b = op.rhs(u, None, n, tau, "dirichlet")
+    got = host(un)
+    assert np.linalg.norm(b - op.apply(got, n, h, tau, "dirichlet")) <= rtol * (1 + 1e-6) * np.linalg.norm(b)
+    xs = exact.solve_dirichlet(b, n, h, tau)
+    kappa = exact.condition_number(grid, n, h, tau, "dirichlet")
+    assert np.linalg.norm(got - xs) <= kappa * rtol * np.linalg.norm(xs)
