@@ -137,7 +137,21 @@ def test_train_step_gradient_loss_and_adam():
         ref_loss += l / batch
         ref_grad += gr / batch
     assert abs(loss - ref_loss) <= 1e-3 * ref_loss
-    assert np.linalg.norm(grad - ref_grad) <= 2e-2 * np.linalg.norm(ref_grad)
+    assert np.linalg.norm(grad - ref_grad) <= 2e-3 * np.linalg.norm(ref_grad)
+    # Per weight and bias group.  Both sides round the same tensors to bf16, so what remains is the
+    # FP32 accumulation order and the rare bf16 rounding that the FP32 pre-activation decides
+    # differently from the FP64 one (a flip of one 2^-8 ulp in one of ~1e5 stored values): each
+    # group agrees to a small multiple of FP32 sums over a few thousand voxels.
+    dev_groups, ref_groups = cnn.unpack(grad), cnn.unpack(ref_grad)
+    errs = []
+    for li, ((gw, gb), (rw, rb)) in enumerate(zip(dev_groups, ref_groups)):
+        for name, g, r in (("W", gw, rw), ("b", gb, rb)):
+            g, r = g.ravel(), r.ravel()
+            rel = np.linalg.norm(g - r) / np.linalg.norm(r)
+            big = np.abs(r) > 1e-2 * np.abs(r).max()
+            errs.append((f"{name}{li + 1}", rel, np.abs(g - r).max() / np.abs(r).max(),
+                         int(np.sum(np.sign(g[big]) != np.sign(r[big])))))
+    assert all(rel <= 2e-3 and amax <= 5e-3 and flips == 0 for _, rel, amax, flips in errs), errs
     # first Adam step from zero moments: theta - lr g / (|g| + eps), on the device's own gradient
     w1 = net.get_weights().astype(np.float64)
     expect = theta.astype(np.float64) - 1e-3 * grad / (np.abs(grad) + 1e-8)
