@@ -56,8 +56,6 @@ def main():
     ap.add_argument("--workload", default="heat928")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed steps (for profiling runs)")
-    ap.add_argument("--persistent", type=int, default=None,
-                    help="tbs_opts.persistent for the CG kernels (default: the library's)")
     ap.add_argument("--solver", default="learned_backoff", choices=list(SOLVERS),
                     help="solver of the timed steps (the others are timed over the same steps in the extras)")
     ap.add_argument("--probe", default=None,
@@ -113,8 +111,7 @@ def main():
     if suse and net is None:
         raise SystemExit("solver %s needs the trained weights %s.f32" % (args.solver, WEIGHTS))
     PREC = tbs.PREC_MIXED if sprec == "mixed" else tbs.PREC_FP64
-    popt = {} if args.persistent is None else {"persistent": args.persistent}
-    ctx.set_opts(poll_every=1, guess_backoff=sbackoff, guess_test=stest, **popt)
+    ctx.set_opts(poll_every=1, guess_backoff=sbackoff, guess_test=stest)
     ctx.ensure_workspace(PREC)
 
     def step(prec, use_net):
@@ -129,7 +126,7 @@ def main():
     torch.cuda.synchronize()
     ua.copy_(u0)
     # the backoff counters restart with the timed steps
-    ctx.set_opts(poll_every=1, guess_backoff=sbackoff, guess_test=stest, **popt)
+    ctx.set_opts(poll_every=1, guess_backoff=sbackoff, guess_test=stest)
     ctx.ensure_workspace(PREC)
     torch.cuda.synchronize()
 

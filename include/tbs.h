@@ -121,12 +121,6 @@ typedef struct {
                               products), kept if that A-norm drops, i.e. 2 gamma r0.du - gamma^2
                               du.A du > 0; for the backoff a kept guess that does not halve the plain
                               guess's FP64 residual counts as a rejection. */
-  int persistent;          /* CG iteration kernels: 1 = launch only as many workgroups as the GPU holds
-                              at once, each walking the tiles in rounds (neighbouring tiles march the
-                              same planes together and share their halo lines in L2); n > 1 = at most
-                              n workgroups (the same scheme with an explicit cap); 0 = one workgroup
-                              per tile.  Iterates change at rounding level (dot products group their
-                              terms by workgroup). */
 } tbs_opts;
 
 /* ---------------------------------------------------------------- context ---------------- */

@@ -59,7 +59,7 @@ class Opts(ctypes.Structure):
                 ("max_sweeps", ctypes.c_int), ("poll_every", ctypes.c_int), ("zchunk", ctypes.c_int),
                 ("tile_order", ctypes.c_int), ("nt_store", ctypes.c_int), ("fused_cg", ctypes.c_int),
                 ("coarse_guess", ctypes.c_int), ("coarse_rtol", ctypes.c_double), ("guess_backoff", ctypes.c_int),
-                ("guess_test", ctypes.c_int), ("persistent", ctypes.c_int)]
+                ("guess_test", ctypes.c_int)]
 
 
 _vp, _i64p, _dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
@@ -199,9 +199,9 @@ class Context:
 
     def set_opts(self, inner_rtol=1e-6, inner_max_iter=500, max_sweeps=12, poll_every=4, zchunk=0,
                  tile_order=0, nt_store=0, fused_cg=1, coarse_guess=0, coarse_rtol=1e-2, guess_backoff=0,
-                 guess_test=0, persistent=0):
+                 guess_test=0):
         o = Opts(inner_rtol, inner_max_iter, max_sweeps, poll_every, zchunk, tile_order, nt_store, fused_cg,
-                 coarse_guess, coarse_rtol, guess_backoff, guess_test, persistent)
+                 coarse_guess, coarse_rtol, guess_backoff, guess_test)
         _check(_lib.tbs_set_opts(self._h, ctypes.byref(o)), "tbs_set_opts")
         # options can change the workspace layout (partial-sum count, coarse-guess region): the
         # library drops its binding then; rebind the buffer if it still holds the minimum

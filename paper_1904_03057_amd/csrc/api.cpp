@@ -301,7 +301,6 @@ extern "C" int tbs_setup(tbs_ctx** out, const int64_t grid[3], int degree, const
   c->opts.fused_cg = 1;
   c->opts.coarse_guess = 0;
   c->opts.coarse_rtol = 1e-2;
-  c->opts.persistent = 0;
   *out = c;
   return TBS_OK;
 }
@@ -458,13 +457,12 @@ extern "C" int tbs_set_opts(tbs_ctx* c, const tbs_opts* o) {
     c->opts.inner_rtol = 1e-6; c->opts.inner_max_iter = 500; c->opts.max_sweeps = 12; c->opts.poll_every = 4;
     c->opts.zchunk = 0; c->opts.tile_order = 0; c->opts.nt_store = 0; c->opts.fused_cg = 1;
     c->opts.coarse_guess = 0; c->opts.coarse_rtol = 1e-2; c->opts.guess_backoff = 0; c->opts.guess_test = 0;
-    c->opts.persistent = 0;
   } else {
     if (!(o->inner_rtol > 0 && o->inner_rtol < 1) || o->inner_max_iter < 1 || o->max_sweeps < 1 ||
         o->poll_every < 1 || o->zchunk < 0 || o->tile_order < 0 || o->tile_order > 1 || o->nt_store < 0 ||
         o->nt_store > 1 || o->fused_cg < 0 || o->fused_cg > 1 || o->coarse_guess < 0 || o->coarse_guess > 1 ||
         !(o->coarse_rtol > 0 && o->coarse_rtol < 1) || o->guess_backoff < 0 || o->guess_backoff > 1 ||
-        o->guess_test < 0 || o->guess_test > 1 || o->persistent < 0)
+        o->guess_test < 0 || o->guess_test > 1)
       return set_err(TBS_E_INVAL, "bad options");
     if (o->coarse_guess) {
       if (c->transform_degree) return set_err(TBS_E_INVAL, "coarse guess on a transform context");
@@ -612,7 +610,7 @@ static int resid_async(tbs_ctx* c, const double* x, const double* b, void* r, in
   const int ps = prof_begin(c, 8, -1, (double)c->N * (16 + (r ? (r_dt == TBS_F32 ? 4 : 8) : 0)));
   HIPCHK(launch_resid(a, c->n, c->bc, r_dt == TBS_F32 ? 1 : 0, c->st));
   prof_end(c, ps);
-  HIPCHK(launch_finalize(fin_op, part0(c), part1(c), stencil_blocks(a, M_RESID, 8), scal(c, slot), rtol, c->st));
+  HIPCHK(launch_finalize(fin_op, part0(c), part1(c), stencil_blocks(a, M_RESID, 8, c->n, c->bc), scal(c, slot), rtol, c->st));
   return TBS_OK;
 }
 
@@ -676,7 +674,7 @@ extern "C" int tbs_residual_noalloc(tbs_ctx* c, const double* x, const double* b
     return set_err(TBS_E_INVAL, "norms must not alias the arrays");
   if (r && r_dt != TBS_F64 && r_dt != TBS_F32) return set_err(TBS_E_INVAL, "r dtype must be F64 or F32");
   StencilArgs a = base_args(c);
-  const int nb = stencil_blocks(a, M_RESID, 8);
+  const int nb = stencil_blocks(a, M_RESID, 8, c->n, c->bc);
   if (nb > kNoAllocMaxBlocks)
     return set_err(TBS_E_INVAL, "residual launch needs %d workgroups, the static buffer holds %d", nb, kNoAllocMaxBlocks);
   if (c->st) {
@@ -758,14 +756,13 @@ static int cg1_async(tbs_ctx* c, const CgArrays& A, int dt, int k) {
   a.io0 = A.x;
   a.scal = scal(c, SC_CG);
   a.first = (k == 0);
-  a.persist = c->opts.persistent;
   const double tc = dt == 0 ? 8 : 4, tp = dt == 0 ? 8 : (dt == 1 ? 4 : 2);
   // first iteration: read r, write p and q; later: read r, p_old, x, write p, q, x
   const double b1 = (double)c->N * (k == 0 ? (2 * tc + tp) : (4 * tc + 2 * tp));
   int ps = prof_begin(c, 5 + dt, k, b1);
   HIPCHK(launch_cg1(a, c->n, c->bc, dt, c->st));
   prof_end(c, ps);
-  HIPCHK(launch_finalize(FIN_ALPHA, part0(c), nullptr, stencil_last_blocks(), scal(c, SC_CG),
+  HIPCHK(launch_finalize(FIN_ALPHA, part0(c), nullptr, stencil_blocks(a, M_CG1, dt == 0 ? 8 : 4, c->n, c->bc), scal(c, SC_CG),
                          0.0, c->st));
   ps = prof_begin(c, dt == 0 ? 9 : 10, k, (double)c->N * 3 * tc);
   HIPCHK(launch_cg2(A.r, A.q, c->N, dt == 0 ? 0 : 1, part0(c), scal(c, SC_CG), c->st));
@@ -791,14 +788,13 @@ static int cgf_async(tbs_ctx* c, const CgArrays& A, int dt, int k) {
   a.io0 = A.x;
   a.scal = scal(c, SC_CG);
   a.first = (k == 0);
-  a.persist = c->opts.persistent;
   const double tp = dt == 1 ? 4 : 2;
   // first iteration: read r, write r, p, q; later: read r, q, p_old, x, write r, p, q, x
   const double b1 = (double)c->N * (k == 0 ? (12 + tp) : (2 * (12 + tp)));
   int ps = prof_begin(c, dt == 1 ? 11 : 12, k, b1);
   HIPCHK(launch_cgf(a, c->n, c->bc, dt, c->st));
   prof_end(c, ps);
-  HIPCHK(launch_finalize(FIN_FUSED, part0(c), part1(c), stencil_last_blocks(), scal(c, SC_CG), 0.0, c->st,
+  HIPCHK(launch_finalize(FIN_FUSED, part0(c), part1(c), stencil_blocks(a, M_CGF, 4, c->n, c->bc), scal(c, SC_CG), 0.0, c->st,
                          part2(c), part3(c)));
   return TBS_OK;
 }
@@ -1224,7 +1220,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
       // a bf16-stored direction limits the attainable inner accuracy: never ask it for less than 1e-4
       const double eta = std::max(std::max(c->opts.inner_rtol, dt == 2 ? 1e-4 : 0.0), 0.5 * rtol / rel);
       HIPCHK(launch_fill(d32, 1, c->N, c->st));
-      HIPCHK(launch_finalize(FIN_INIT, part0(c), part0(c), stencil_blocks(base_args(c), M_RESID, 8), scal(c, SC_CG),
+      HIPCHK(launch_finalize(FIN_INIT, part0(c), part0(c), stencil_blocks(base_args(c), M_RESID, 8, c->n, c->bc), scal(c, SC_CG),
                              eta, c->st));
       int nit = 0;
       const int cap = std::min(c->opts.inner_max_iter, std::max(1, max_iter - total));

@@ -68,7 +68,6 @@ struct StencilArgs {
   int order;                   // tile order: 0 x-tiles fastest, 1 y-tiles fastest
   int nt_store;                // 1: outputs written with non-temporal stores
   RobinCorner rb;              // BC_ROBIN corner blocks
-  int persist;                 // 0: one workgroup per tile; 1: only as many as are resident; n > 1: at most n
   double rscale;               // RESID: factor (a power of two) on the stored residual and its sums
 };
 

@@ -13,40 +13,66 @@
 #define STENCIL_CG_TY 16
 #endif
 #ifndef STENCIL_CGF_TY
-#define STENCIL_CGF_TY 16
+#define STENCIL_CGF_TY 32
 #endif
 #ifndef STENCIL_CG_PF
 #define STENCIL_CG_PF 1
 #endif
 #ifndef STENCIL_RESID_TY
-#define STENCIL_RESID_TY 8
+#define STENCIL_RESID_TY 16
+#endif
+#ifndef STENCIL_RESID_WY
+#define STENCIL_RESID_WY 8
+#endif
+#ifndef STENCIL_F64_WY
+#define STENCIL_F64_WY 8
 #endif
 
 namespace tbs {
 
 constexpr int kTileX = 64;
-constexpr int kTileYMin2 = STENCIL_RESID_TY < STENCIL_CGF_TY ? STENCIL_RESID_TY : STENCIL_CGF_TY;
-constexpr int kTileY = kTileYMin2 < STENCIL_TY ? kTileYMin2 : STENCIL_TY;  // smallest tile height: sizes the partial-sum buffers
+constexpr int imin(int a, int b) { return a < b ? a : b; }
+// smallest tile height of any stencil launch (the one-kernel FP32 CG iteration takes 16 rows or
+// more): sizes the partial-sum buffers
+constexpr int kTileY = imin(imin(STENCIL_RESID_TY, STENCIL_TY), imin(STENCIL_CG_TY, 16));
 constexpr int kTileYPlan = 16;  // tile height the z-chunk plan assumes
+constexpr int kLdsMax = 160 * 1024;  // LDS one workgroup may hold on gfx950
 
-// Tile height per (mode, compute precision): taller tiles re-read fewer halo rows; the FP64
-// kernels keep 16 rows for register room, and the FP64 residual (two FP64 inputs) 8.
-constexpr int stencil_tile_y(int mode, int compute_bytes) {
-  return compute_bytes == 4 ? ((mode == M_APPLY) ? 32 : (mode == M_CG1 ? STENCIL_CG_TY : (mode == M_CGF ? STENCIL_CGF_TY : 16)))
-                            : (mode == M_RESID ? STENCIL_RESID_TY : 16);
+// LDS of the one-kernel FP32 CG iteration (degree n, tile height ty, 64 columns): staged plane
+// (x halo of at most 8 columns a side: one 16-byte vector of bf16), the two x-pass planes, the p
+// and r rings, the reduction slots, and the Robin corner tables and z-accumulators (one-element
+// placeholders otherwise).  An upper bound of what the kernel declares (it asserts so).
+constexpr int cgf_lds_bytes(int n, int ty, int bc) {
+  return 4 * ((ty + 2 * n) * (64 + 16) + 2 * (ty + 2 * n) * 64 + (2 * n + 3) * ty * 64) + 8 * 4 * (ty / 4) +
+         (bc == BC_ROBIN ? 4 * (4 * kRobinMaxZ * kRobinMaxZ + (2 * (n / 2) + 1) * ty * 64) : 8);
+}
+
+// Tile height per (mode, compute precision, degree, boundary): taller tiles re-read fewer halo
+// rows.  The FP64 kernels take 16 rows in eight row waves of two rows (the FP64 ring and column
+// windows of two rows leave room for more waves per SIMD than four rows in four waves).  The
+// one-kernel FP32 CG iteration takes 32 rows (eight row waves of four rows: the same registers per
+// thread as 16 rows in four waves) wherever its LDS fits one workgroup, else 16.
+constexpr int stencil_tile_y(int mode, int compute_bytes, int n, int bc) {
+  return compute_bytes == 4
+             ? ((mode == M_APPLY) ? 32
+                                  : (mode == M_CG1 ? STENCIL_CG_TY
+                                                   : (mode == M_CGF ? (cgf_lds_bytes(n, STENCIL_CGF_TY, bc) <= kLdsMax
+                                                                           ? STENCIL_CGF_TY : 16)
+                                                                    : 16)))
+             : (mode == M_RESID ? STENCIL_RESID_TY : 16);
+}
+// Row waves per workgroup: four for the FP32 kernels, except the one-kernel CG iteration, whose
+// waves keep four rows each; eight for the FP64 kernels.
+constexpr int stencil_tile_wy(int mode, int compute_bytes, int n, int bc) {
+  return (mode == M_CGF && compute_bytes == 4) ? stencil_tile_y(mode, compute_bytes, n, bc) / 4
+                                               : (mode == M_RESID ? STENCIL_RESID_WY
+                                                                  : (compute_bytes == 8 ? STENCIL_F64_WY : 4));
 }
 // One stencil launch of degree N for a (mode, input, compute, output) type combination and
 // boundary condition BC; defined in stencil_kernel.h and instantiated per degree and boundary
 // condition by stencil_inst.hip.
 template <int N, int MODE, typename Tin, typename Tc, typename Tout, int BC>
 hipError_t launch_bcx(const StencilArgs& a, bool vec, hipStream_t st);
-
-// Workgroups (= partial sums written) of the last stencil launch on this thread: the tile count,
-// or the resident-workgroup count of a persistent launch.
-extern thread_local int g_stencil_blocks;
-inline int stencil_last_blocks() { return g_stencil_blocks; }
-// Workgroups of `kernel` (block threads each) the whole GPU holds at once (0 if unknown).
-int resident_blocks(const void* kernel, int block);
 
 template <int N, int MODE, typename Tin, typename Tc, typename Tout>
 inline hipError_t launch_bc(const StencilArgs& a, int bc, bool vec, hipStream_t st) {
@@ -56,7 +82,7 @@ inline hipError_t launch_bc(const StencilArgs& a, int bc, bool vec, hipStream_t 
 }
 
 // Number of workgroups (= partial sums written) of a stencil launch of this mode.
-int stencil_blocks(const StencilArgs& a, int mode, int compute_bytes);
+int stencil_blocks(const StencilArgs& a, int mode, int compute_bytes, int n, int bc);
 
 // stencil.hip
 hipError_t launch_apply(const StencilArgs& a, int n, int bc, int in_dt, int out_dt, hipStream_t st);

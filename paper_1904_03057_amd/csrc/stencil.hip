@@ -20,18 +20,8 @@ static hipError_t launch_n(const StencilArgs& a, int n, int bc, hipStream_t st) 
   return hipErrorInvalidValue;
 }
 
-thread_local int g_stencil_blocks = 0;
-
-int resident_blocks(const void* kernel, int block) {
-  int per_cu = 0, dev = 0, cus = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess) return 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  return per_cu * cus;
-}
-
-int stencil_blocks(const StencilArgs& a, int mode, int compute_bytes) {
-  const int ty = stencil_tile_y(mode, compute_bytes);
+int stencil_blocks(const StencilArgs& a, int mode, int compute_bytes, int n, int bc) {
+  const int ty = stencil_tile_y(mode, compute_bytes, n, bc);
   const int wx = (mode == M_APPLY && compute_bytes == 4) ? STENCIL_APPLY_WX : 1;
   return ((a.nx + 64 * wx - 1) / (64 * wx)) * ((a.ny + ty - 1) / ty) * a.nchunks;
 }

@@ -1,6 +1,6 @@
 #pragma once
-// Stencil kernel template (private to the stencil translation units: the kernels are instantiated
-// per basis degree in stencil_n<k>.hip, so the degrees compile in parallel; the dtype / mode
+// Stencil kernel template (private to the stencil translation units: stencil_inst.hip instantiates
+// it once per basis degree and boundary condition, so those compile in parallel; the dtype / mode
 // dispatch lives in stencil.hip).
 //
 // On-the-fly tensor B-spline operator for gfx950: the paper's separable domain kernels
@@ -14,8 +14,8 @@
 // which expands to (Mx My Mz + ax Kx My Mz + ay Mx Ky Mz + az Mx My Kz) u.  Symmetric taps are
 // applied to pair sums (u_{i-j} + u_{i+j}), and every accumulation is an explicit FMA chain.
 //
-// Execution ("2.5-D" streaming): a workgroup of WX x 256 threads owns a 64 WX x TY tile of the x-y plane and
-// marches along z through its chunk of planes.  Each input plane tile (halo n rows in y, halo HX
+// Execution ("2.5-D" streaming): a workgroup of WX x WY waves (WX column groups of 64 lanes, WY row
+// groups of TY / WY rows) owns a 64 WX x TY tile of the x-y plane and marches along z through its chunk of planes.  Each input plane tile (halo n rows in y, halo HX
 // columns in x, HX = n rounded up to the 16-byte vector width) is fetched with 16-byte loads
 // one plane ahead into registers, converted/transformed and staged in LDS.  The x-pass (lanes =
 // columns) and the y-pass (a register column window per thread) run from LDS; the z-pass is
@@ -39,9 +39,9 @@ template <> __device__ __forceinline__ double to_c<uint16_t, double>(uint16_t v)
 template <typename Ts, typename Tc> __device__ __forceinline__ Ts from_c(Tc v) { return (Ts)v; }
 template <> __device__ __forceinline__ uint16_t from_c<uint16_t, float>(float v) { return f32_to_bf16(v); }
 
-template <int N, int TY, int MODE, typename Tin, typename Tc, typename Tout, int BC, bool VEC, int WX>
-__global__ __launch_bounds__(256 * WX) __attribute__((amdgpu_waves_per_eu(BC == BC_ROBIN ? 2 : 1))) void stencil_kernel(StencilArgs a) {
-  constexpr int NT = 256 * WX;                     // threads: WX column groups of 64 x 4 waves
+template <int N, int TY, int MODE, typename Tin, typename Tc, typename Tout, int BC, bool VEC, int WX, int WY>
+__global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC == BC_ROBIN ? 2 : 1))) void stencil_kernel(StencilArgs a) {
+  constexpr int NT = 64 * WX * WY;                 // threads: WX column groups of 64 x WY row waves
   constexpr int VE = VEC ? 16 / (int)sizeof(Tin) : 1;
   using Raw = VecN<Tin, VE>;   // staged input (u, u_prev, x, p_old)
   using RawC = VecN<Tc, VE>;   // companion compute-precision vectors (q of RHS; r and x of CG1)
@@ -56,11 +56,11 @@ __global__ __launch_bounds__(256 * WX) __attribute__((amdgpu_waves_per_eu(BC == 
   constexpr int NVC = (CORE + NT - 1) / NT;        // core vectors per thread (slots 0..NVC-1)
   constexpr int NVH = (HALO + NT - 1) / NT;        // halo vectors per thread
   constexpr int NV = NVC + NVH;
-  constexpr int RPW = TY / 4;                      // output rows per wave
+  constexpr int RPW = TY / WY;                     // output rows per wave
   constexpr bool CG = (MODE == M_CG1 || MODE == M_CGF);
   constexpr bool FUSED = (MODE == M_CGF);
   constexpr int QD = CG ? N + 1 : 1;  // depth of the centre-value rings (CG1, CGF)
-  static_assert(TY % 4 == 0, "TY must be a multiple of 4");
+  static_assert(TY % WY == 0, "TY must be a multiple of the row waves");
 
   __shared__ Tc stage[R * C];
   __shared__ Tc su[R * TX];
@@ -71,11 +71,14 @@ __global__ __launch_bounds__(256 * WX) __attribute__((amdgpu_waves_per_eu(BC == 
   // is never the one the previous plane's outputs are still reading.
   constexpr int RQD = FUSED ? N + 2 : 1;
   __shared__ Tc rring[FUSED ? RQD * TY * TX : 1];
-  __shared__ double red[4][4 * WX];
+  __shared__ double red[4][WY * WX];
   // BC_ROBIN: corner blocks in compute precision (cm, cvx, cwy, cwz, each kRobinMaxZ^2)
   constexpr int RBT = kRobinMaxZ * kRobinMaxZ;
   __shared__ Tc rbt[BC == BC_ROBIN ? 4 * RBT : 1];
   __shared__ Tc zl[BC == BC_ROBIN ? (2 * (N / 2) + 1) * TY * TX : 1];
+  static_assert(sizeof(stage) + sizeof(su) + sizeof(sv) + sizeof(cring) + sizeof(rring) + sizeof(red) + sizeof(rbt) +
+                        sizeof(zl) <= (FUSED ? cgf_lds_bytes(N, TY, BC) : kLdsMax),
+                "LDS of the workgroup");
 
   if (CG && a.scal->done) return;
 
@@ -96,15 +99,9 @@ __global__ __launch_bounds__(256 * WX) __attribute__((amdgpu_waves_per_eu(BC == 
   const int lane = tid & 63;
   const int wv = tid >> 6;
   const int col = (wv % WX) * 64 + lane;           // tile column of this lane
-  const int wave = wv / WX;                        // row group 0..3
+  const int wave = wv / WX;                        // row group 0..WY-1
 
-  // persistent launches (grid smaller than the tile count) walk the tiles in rounds of gridDim.x:
-  // the blocks of one round start together and march the same z-planes in step, so the halo rows
-  // and columns their neighbours fetch are still in L2; a plain launch has one round
-  double part0 = 0.0, part1 = 0.0, part2 = 0.0, part3 = 0.0;
-  for (int tile = blockIdx.x; tile < a.nblocks; tile += gridDim.x) {
-  const int r0 = tile - (int)blockIdx.x;  // first tile of this round
-  const int bid = r0 + xcd_remap(blockIdx.x, min((int)gridDim.x, a.nblocks - r0));
+  const int bid = xcd_remap(blockIdx.x, a.nblocks);
   // logical tile order (x- or y-tiles fastest, then the other, then z-chunks): the tiles an XCD
   // runs at the same time are neighbours whose halo cache lines meet in that XCD's L2
   int txi, tyi, czi;
@@ -198,6 +195,7 @@ __global__ __launch_bounds__(256 * WX) __attribute__((amdgpu_waves_per_eu(BC == 
   RawC px[PF][NVC];
   RawC pq[FUSED ? PF : 1][FUSED ? NV : 1];  // CGF: q_old
   int pk[PF] = {};  // plane index held in each prefetch slot
+  double part0 = 0.0, part1 = 0.0, part2 = 0.0, part3 = 0.0;
 
   auto fetch = [&](int k, const int sl) {
     bool pvalid = true;
@@ -329,7 +327,7 @@ __global__ __launch_bounds__(256 * WX) __attribute__((amdgpu_waves_per_eu(BC == 
             cring[(qs * TY + wave * RPW + i) * TX + col] = stage[(wave * RPW + i + N) * C + col + HX];
         }
         // x-pass over all R staged rows (rows dealt to the waves round-robin)
-        for (int r = wave; r < R; r += 4) {
+        for (int r = wave; r < R; r += WY) {
           const Tc* row = stage + r * C + HX + col;
           const Tc c0 = row[0];
           Tc U = m[0] * c0;
@@ -497,8 +495,6 @@ __global__ __launch_bounds__(256 * WX) __attribute__((amdgpu_waves_per_eu(BC == 
       }
     }
   }
-  __syncthreads();  // the next tile restages the LDS buffers the last outputs of this one read
-  }
 
   if (CG || MODE == M_RESID) {
     part0 = wave_sum(part0);
@@ -512,7 +508,7 @@ __global__ __launch_bounds__(256 * WX) __attribute__((amdgpu_waves_per_eu(BC == 
     if (tid == 0) {
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
-      for (int q = 0; q < 4 * WX; ++q) { s0 += red[0][q]; s1 += red[1][q]; s2 += red[2][q]; s3 += red[3][q]; }
+      for (int q = 0; q < WY * WX; ++q) { s0 += red[0][q]; s1 += red[1][q]; s2 += red[2][q]; s3 += red[3][q]; }
       a.part0[blockIdx.x] = s0;
       if (MODE == M_RESID || FUSED) a.part1[blockIdx.x] = s1;
       if (FUSED) { a.part2[blockIdx.x] = s2; a.part3[blockIdx.x] = s3; }
@@ -523,10 +519,15 @@ __global__ __launch_bounds__(256 * WX) __attribute__((amdgpu_waves_per_eu(BC == 
 // ------------------------------------------------------------------------------------------
 // host-side launch helpers
 
-// Tile shape per (mode, compute type): the arithmetic-heavy FP32 apply uses 128 x 32 tiles
-// (512 threads: the x halo costs fewer partial cache lines per row); the kernels that write
-// per-block partial sums keep 64 x 16 tiles (the host sizes their partial-sum buffers for it).
-template <int MODE, typename Tc> constexpr int tile_y() { return stencil_tile_y(MODE, (int)sizeof(Tc)); }
+// Tile shape per (degree, mode, compute type, boundary): heights and row waves from stencil.h (the
+// host sizes the partial-sum buffers for the smallest height); the FP32 apply may take WX column
+// groups (STENCIL_APPLY_WX, one by default).
+template <int N, int MODE, typename Tc, int BC> constexpr int tile_y() {
+  return stencil_tile_y(MODE, (int)sizeof(Tc), N, BC);
+}
+template <int N, int MODE, typename Tc, int BC> constexpr int tile_wy() {
+  return stencil_tile_wy(MODE, (int)sizeof(Tc), N, BC);
+}
 template <int MODE, typename Tc> constexpr int tile_wx() {
   return (MODE == M_APPLY && sizeof(Tc) == 4) ? STENCIL_APPLY_WX : 1;
 }
@@ -535,30 +536,19 @@ template <int MODE, typename Tc> constexpr int tile_wx() {
 // instances compile in parallel; stencil.h dispatches on the run-time boundary condition).
 template <int N, int MODE, typename Tin, typename Tc, typename Tout, int BC>
 hipError_t launch_bcx(const StencilArgs& a0, bool vec, hipStream_t st) {
-  constexpr int TY = tile_y<MODE, Tc>();
+  constexpr int TY = tile_y<N, MODE, Tc, BC>();
   constexpr int WX = tile_wx<MODE, Tc>();
+  constexpr int WY = tile_wy<N, MODE, Tc, BC>();
+  static_assert(TY >= kTileY, "the partial-sum buffers hold one sum per tile of kTileY rows");
   StencilArgs a = a0;  // geometry for this tile shape
   a.tiles_x = (a.nx + 64 * WX - 1) / (64 * WX);
   a.tiles_y = (a.ny + TY - 1) / TY;
   a.nblocks = a.tiles_x * a.tiles_y * a.nchunks;
-  auto kv = stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC, true, WX>;
-  auto ks = stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC, false, WX>;
-  int blocks = a.nblocks;
-  if (a.persist == 1) {
-    // as many workgroups as the GPU holds at once (queried once per kernel instance)
-    static const int resident[2] = {resident_blocks((const void*)ks, 256 * WX),
-                                    resident_blocks((const void*)kv, 256 * WX)};
-    const int r = resident[vec ? 1 : 0];
-    if (r > 0 && r < blocks) blocks = r;
-  } else if (a.persist > 1 && a.persist < blocks) {
-    blocks = a.persist;  // an explicit cap
-  }
-  g_stencil_blocks = blocks;
-  dim3 grid(blocks), block(256 * WX);
+  dim3 grid(a.nblocks), block(64 * WX * WY);
   if (vec)
-    hipLaunchKernelGGL(kv, grid, block, 0, st, a);
+    hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC, true, WX, WY>), grid, block, 0, st, a);
   else
-    hipLaunchKernelGGL(ks, grid, block, 0, st, a);
+    hipLaunchKernelGGL((stencil_kernel<N, TY, MODE, Tin, Tc, Tout, BC, false, WX, WY>), grid, block, 0, st, a);
   return hipGetLastError();
 }
 

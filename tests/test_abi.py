@@ -106,7 +106,7 @@ def test_set_opts_validation_without_gpu():
     assert lib.tbs_set_opts(p, ctypes.byref(good)) == tbs.OK
     assert lib.tbs_set_opts(p, None) == tbs.OK
     for field, bad in (("guess_backoff", 2), ("guess_backoff", -1), ("fused_cg", 2), ("inner_rtol", 0.0),
-                       ("coarse_rtol", 1.0), ("poll_every", 0), ("guess_test", 2), ("guess_test", -1), ("persistent", -1)):
+                       ("coarse_rtol", 1.0), ("poll_every", 0), ("guess_test", 2), ("guess_test", -1)):
         o = tbs.Opts(1e-6, 500, 12, 4, 0, 0, 0, 1, 0, 1e-2, 0)
         setattr(o, field, bad)
         assert lib.tbs_set_opts(p, ctypes.byref(o)) == tbs.E_INVAL, field
@@ -124,8 +124,9 @@ def test_residual_noalloc_validates_before_any_hip_call():
     assert lib.tbs_residual_noalloc(p, a, b, a, tbs.F64, nrm) == tbs.E_INVAL            # r aliases x
     assert lib.tbs_residual_noalloc(p, a, b, r, tbs.BF16, nrm) == tbs.E_INVAL           # bad r dtype
     lib.tbs_destroy(p)
-    # a plane of 19200 x 2400 points needs 300 * 300 residual workgroups: more than the static buffer holds
-    rc, p = _setup(grid=(64 * 300, 8 * 300, 16), n=2)
+    # a plane of 19200 x 4800 points needs 300 * 300 residual workgroups (64 x 16 tiles): more than
+    # the static buffer holds
+    rc, p = _setup(grid=(64 * 300, 16 * 300, 16), n=2)
     assert rc == tbs.OK
     assert lib.tbs_residual_noalloc(p, a, b, r, tbs.F64, nrm) == tbs.E_INVAL
     assert b"static buffer" in tbs.lib().tbs_last_error()
