@@ -164,6 +164,7 @@ struct tbs_ctx {
   int64_t cgrid[3];
   // learned-guess backoff (opts.guess_backoff): consecutive rejections, steps left to skip
   int guess_rejects, guess_wait;
+  int cgf_pend;  // host copy of the pending x-update count of the one-kernel CG (for its byte count)
   // CG session state (tbs_cg_begin / tbs_cg_step)
   int cg_active, cg_dt, cg_enq;
   void* cg_x;
@@ -772,9 +773,10 @@ static int cg1_async(tbs_ctx* c, const CgArrays& A, int dt, int k) {
 }
 
 // One-kernel CG iteration k (FP32 vectors): r_k = r_{k-1} - alpha q_{k-1}, p_k = r_k + beta p_{k-1},
-// x += alpha p_{k-1}, q_k = A p_k and the FP64 partial sums of p.q, r.q, q.q and r.r in one stencil
-// launch, then one reduction.  r, p and q alternate between two arrays (halo reads of the old
-// values and writes of the new ones overlap in one launch).
+// q_k = A p_k and the FP64 partial sums of p.q, r.q, q.q and r.r in one stencil launch, then one
+// reduction; every second iteration also x += alpha2 p_{k-2} + alpha p_{k-1} (the two pending
+// updates).  r, p and q alternate between two arrays (halo reads of the old values and writes of
+// the new ones overlap in one launch).
 static int cgf_async(tbs_ctx* c, const CgArrays& A, int dt, int k) {
   StencilArgs a = base_args(c);
   void* R[2] = {A.r, A.r2};
@@ -789,8 +791,11 @@ static int cgf_async(tbs_ctx* c, const CgArrays& A, int dt, int k) {
   a.scal = scal(c, SC_CG);
   a.first = (k == 0);
   const double tp = dt == 1 ? 4 : 2;
-  // first iteration: read r, write r, p, q; later: read r, q, p_old, x, write r, p, q, x
-  const double b1 = (double)c->N * (k == 0 ? (12 + tp) : (2 * (12 + tp)));
+  // first iteration: read r, write r, p, q; later: read r, q, p_old, write r, p, q, and on the
+  // iterations that advance x also read x, p_{k-2} and write x
+  const int pend = k == 0 ? 0 : c->cgf_pend;
+  const double b1 = (double)c->N * (k == 0 ? (12 + tp) : (pend == 2 ? 24 + 3 * tp : 2 * (8 + tp)));
+  c->cgf_pend = (pend == 2 ? 0 : pend) + 1;
   int ps = prof_begin(c, dt == 1 ? 11 : 12, k, b1);
   HIPCHK(launch_cgf(a, c->n, c->bc, dt, c->st));
   prof_end(c, ps);
@@ -821,6 +826,7 @@ static int cg_loop(tbs_ctx* c, const CgArrays& A, int dt, int k0, int max_iter, 
   if (!keep_pending) {
     HIPCHK(launch_flush(A.x, A.p[0], A.p[1], c->N, dt, scal(c, SC_CG), c->st));
     HIPCHK(launch_finalize(FIN_CLEAR_PENDING, nullptr, nullptr, 0, scal(c, SC_CG), 0.0, c->st));
+    c->cgf_pend = 0;
   }
   *nit = s.nit;
   if (s.status == TBS_E_BREAKDOWN) return set_err(TBS_E_BREAKDOWN, "CG breakdown after %d iterations", s.nit);

@@ -23,11 +23,15 @@ struct Scalars {
   double rr0;     // r.r at start
   double out;     // scratch result (dot, norms)
   double out2;
+  double alpha2;  // alpha of iteration nit-2 (one-kernel FP32 CG, two pending updates)
   int done;       // 1: converged, breakdown or trivial system -> every CG kernel returns at once
   int nit;        // completed CG iterations
   int status;     // 0 ok, -4 breakdown
-  int pending;    // 1: x += alpha * p of iteration nit-1 still to be applied
+  // x updates still to apply: 1 = alpha p_{nit-1}; 2 (one-kernel FP32 CG, which advances x every
+  // second iteration) = alpha2 p_{nit-2}, then alpha p_{nit-1}
+  int pending;
 };
+static_assert(sizeof(Scalars) <= 256, "a Scalars slot of the workspace is 256 bytes");
 
 // CG1: one half of a Hestenes-Stiefel iteration (p, x update, q = A p, p.q); CGF: a whole iteration
 // in one kernel (r update, p, x update, q = A p and the dot products p.q, r.q, q.q, r.r).

@@ -183,7 +183,13 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
 
   const Tc beta = (CG && !a.first) ? (Tc)a.scal->beta : (Tc)0;
   const Tc alpha_prev = CG ? (Tc)a.scal->alpha : (Tc)0;
-  const bool xupd = CG && a.io0 != nullptr && !a.first && a.scal->pending;
+  // lazy x update: CG1 applies the one pending update alpha p_{k-1}; CGF advances x every second
+  // iteration, applying alpha2 p_{k-2} (read from the array p_k is about to overwrite, at the own
+  // points only) and then alpha p_{k-1}, one rounding each, so x is bitwise that of one update per
+  // iteration while it is read and written half as often
+  const int npend = CG ? a.scal->pending : 0;
+  const bool xupd = CG && a.io0 != nullptr && !a.first && (FUSED ? npend == 2 : npend != 0);
+  const Tc alpha2 = FUSED ? (Tc)a.scal->alpha2 : (Tc)0;
   const Tc tauc = (Tc)a.t.tau;
 
   // prefetch registers: primary input vector (u / u_prev / p_old / x), secondary (q / r), x (CG1)
@@ -194,6 +200,7 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
   RawC pb[PF][NV];
   RawC px[PF][NVC];
   RawC pq[FUSED ? PF : 1][FUSED ? NV : 1];  // CGF: q_old
+  Raw pp2[FUSED ? PF : 1][FUSED ? NVC : 1];  // CGF: p_{k-2} at the own points (x update)
   int pk[PF] = {};  // plane index held in each prefetch slot
   double part0 = 0.0, part1 = 0.0, part2 = 0.0, part3 = 0.0;
 
@@ -216,6 +223,7 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
         pb[sl][v].x[e] = (Tc)0;
         if (v < NVC) px[sl][v < NVC ? v : 0].x[e] = (Tc)0;
         if (FUSED) pq[FUSED ? sl : 0][FUSED ? v : 0].x[e] = (Tc)0;
+        if (FUSED && v < NVC) pp2[FUSED ? sl : 0][FUSED && v < NVC ? v : 0].x[e] = (Tin)0;
       }
       if (pvalid && ((valid >> v) & 1u)) {
         const int64_t gi = base + off[v];
@@ -228,8 +236,10 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
           pb[sl][v] = *(const RawC*)((const Tc*)a.in0 + gi);
           if (!a.first) pa[sl][v] = *(const Raw*)((const Tin*)a.in1 + gi);
           if (FUSED && !a.first) pq[FUSED ? sl : 0][FUSED ? v : 0] = *(const RawC*)((const Tc*)a.in2 + gi);
-          if (v < NVC && xupd && inchunk && ((own >> v) & 1u))
+          if (v < NVC && xupd && inchunk && ((own >> v) & 1u)) {
             px[sl][v < NVC ? v : 0] = *(const RawC*)((const Tc*)a.io0 + gi);
+            if (FUSED) pp2[FUSED ? sl : 0][FUSED && v < NVC ? v : 0] = *(const Raw*)((const Tin*)a.out1 + gi);
+          }
         }
       }
     }
@@ -266,7 +276,11 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
             dst[e] = val;
             pn.x[e] = from_c<Tin, Tc>(val);
             rn.x[e] = rv;
-            if (v < NVC) xn.x[e] = fmad(alpha_prev, pold, px[sl][v < NVC ? v : 0].x[e]);
+            if (v < NVC) {
+              Tc xv = px[sl][v < NVC ? v : 0].x[e];
+              if (FUSED) xv = fmad(alpha2, to_c<Tin, Tc>(pp2[FUSED ? sl : 0][FUSED && v < NVC ? v : 0].x[e]), xv);
+              xn.x[e] = fmad(alpha_prev, pold, xv);
+            }
           }
           if (FUSED && v < NVC) {
             const int rs = ((k % RQD) + RQD) % RQD;

@@ -93,30 +93,42 @@ __global__ __launch_bounds__(256) void sub_norm_kernel(T* __restrict__ r, const 
   }
 }
 
-// x <- x + alpha p_{nit-1}, p_{nit-1} = (nit odd ? p1 : p0), only if an update is pending
+// The pending x updates, one rounding each and the older first, as the CG kernels apply them:
+// x + alpha2 p_{nit-2} (two pending) and then + alpha p_{nit-1} (p_{nit-1} = (nit odd ? p1 : p0),
+// p_{nit-2} the other array).
+template <typename T, typename Tp>
+__device__ __forceinline__ T apply_pending(T x, int np, T alpha, T alpha2, const Tp* p, const Tp* pp, int64_t i) {
+  if (np == 2) x = fma(alpha2, Io<Tp>::template ld<T>(pp, i), x);
+  if (np >= 1) x = fma(alpha, Io<Tp>::template ld<T>(p, i), x);
+  return x;
+}
+
+// x <- x + the pending updates
 template <typename T, typename Tp>
 __global__ __launch_bounds__(256) void flush_kernel(T* __restrict__ x, const Tp* __restrict__ p0,
                                                     const Tp* __restrict__ p1, int64_t n, const Scalars* s) {
-  if (!s->pending) return;
-  const T alpha = (T)s->alpha;
+  const int np = s->pending;
+  if (!np) return;
+  const T alpha = (T)s->alpha, alpha2 = (T)s->alpha2;
   const Tp* p = (s->nit & 1) ? p1 : p0;
+  const Tp* pp = (s->nit & 1) ? p0 : p1;
   const int64_t stride = (int64_t)gridDim.x * 256;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
-    x[i] += alpha * Io<Tp>::template ld<T>(p, i);
+    x[i] = apply_pending<T, Tp>(x[i], np, alpha, alpha2, p, pp, i);
 }
 
-// out = base + scale (d + alpha p), the FP32 part formed exactly as flush_kernel forms x + alpha p
+// out = base + scale (d + the pending updates), the FP32 part formed exactly as flush_kernel forms it
 template <typename Tp>
 __global__ __launch_bounds__(256) void refine_add_kernel(double* out, const double* base, const float* __restrict__ d,
                                                          const Tp* __restrict__ p0, const Tp* __restrict__ p1,
                                                          int64_t n, const Scalars* s, double scale) {
-  const bool pending = s->pending != 0;
-  const float alpha = (float)s->alpha;
+  const int np = s->pending;
+  const float alpha = (float)s->alpha, alpha2 = (float)s->alpha2;
   const Tp* p = (s->nit & 1) ? p1 : p0;
+  const Tp* pp = (s->nit & 1) ? p0 : p1;
   const int64_t stride = (int64_t)gridDim.x * 256;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
-    float x = d[i];
-    if (pending) x += alpha * Io<Tp>::template ld<float>(p, i);
+    const float x = apply_pending<float, Tp>(d[i], np, alpha, alpha2, p, pp, i);
     out[i] = fma(scale, (double)x, base[i]);
   }
 }
@@ -225,7 +237,7 @@ __global__ __launch_bounds__(1024) void finalize_kernel(int op, const double* __
   switch (op) {
     case FIN_INIT: {
       s->rr = v0; s->rr0 = v0; s->bb = v1; s->tol2 = rtol * rtol * v1;
-      s->nit = 0; s->status = 0; s->pending = 0; s->alpha = 0.0; s->beta = 0.0;
+      s->nit = 0; s->status = 0; s->pending = 0; s->alpha = 0.0; s->alpha2 = 0.0; s->beta = 0.0;
       int done = (v1 == 0.0) || (v0 <= s->tol2);
       if (!isfinite(v0) || !isfinite(v1)) { s->status = -4; done = 1; }
       s->done = done;
@@ -251,7 +263,8 @@ __global__ __launch_bounds__(1024) void finalize_kernel(int op, const double* __
       // v0 = p_k.q_k, v1 = r_k.q_k, v2 = q_k.q_k, v3 = r_k.r_k of the iteration's recursive residual.
       // alpha from the explicit r_k.r_k; r_{k+1}.r_{k+1} = r.r - 2 alpha r.q + alpha^2 q.q (one step
       // ahead, restarted from the explicit value every iteration) gives beta and the stopping test.
-      s->pending = 0;
+      // The kernel applied the pending x updates only if there were two; this iteration's is added.
+      if (s->pending == 2) s->pending = 0;
       s->pq = v0;
       if (!(v0 > 0.0) || !isfinite(v0) || !isfinite(v1) || !isfinite(v2) || !isfinite(v3)) {
         s->status = -4; s->done = 1; break;
@@ -259,11 +272,12 @@ __global__ __launch_bounds__(1024) void finalize_kernel(int op, const double* __
       const double alpha = v3 / v0;
       double rn = v3 - 2.0 * alpha * v1 + alpha * alpha * v2;
       if (rn < 0.0) rn = 0.0;
+      s->alpha2 = s->alpha;
       s->alpha = alpha;
       s->beta = v3 > 0.0 ? rn / v3 : 0.0;
       s->rr = rn;
       s->nit += 1;
-      s->pending = 1;
+      s->pending += 1;
       if (rn <= s->tol2) s->done = 1;
       break;
     }

@@ -93,19 +93,43 @@ def test_cg_fp32_one_kernel_other_degrees(n, grid, bc):
     assert abs(rel - hist[-1]) <= 1e-3 * hist[-1], (rel, hist[-1])
 
 
-def test_cg_fp32_one_kernel_continuation_bitwise():
-    # r, p and q alternate between two arrays: splitting the iterations over calls changes nothing
+@pytest.mark.parametrize("split", [(4, 5), (3, 6), (1, 1, 7), (2, 2, 2, 3)])
+def test_cg_fp32_one_kernel_continuation_bitwise(split):
+    # r, p and q alternate between two arrays, and x takes its updates two at a time (flushed at the
+    # end of each call, one or two pending): splitting the iterations over calls changes nothing
     grid, n, h, tau, bc = (40, 18, 20), 3, (1 / 40, 1 / 18, 1 / 20), 1e-3, "dirichlet"
     b = dev(rounded(normal_field(grid[::-1], 5), "f32"), "f32")
     ctx = _ctx(grid, n, h, tau, bc, tbs.PREC_FP32)
     x1 = dev(np.zeros(grid[::-1]), "f32")
     ctx.cg_begin(b, x1, 0.0)
-    ctx.cg_step(9)
+    ctx.cg_step(sum(split))
     x2 = dev(np.zeros(grid[::-1]), "f32")
     ctx.cg_begin(b, x2, 0.0)
-    ctx.cg_step(4)
-    ctx.cg_step(5)
+    for k in split:
+        ctx.cg_step(k)
     assert np.array_equal(host(x1), host(x2))
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 6, 7])
+def test_cg_fp32_one_kernel_x_after_k_iterations(k):
+    # the iterate after k one-kernel iterations (0, 1 or 2 updates pending at the end) against the
+    # oracle's Hestenes-Stiefel iterate, and against the two-kernel form, which updates x every
+    # iteration: both apply the same FP32 updates, so their x agree to FP32 rounding of the operator
+    grid, n, bc = (48, 20, 22), 3, "dirichlet"
+    tau, h = 1e-3, tuple(1.0 / N for N in grid)
+    b = rounded(normal_field(grid[::-1], 3), "f32")
+    xs = []
+    for fused in (1, 0):
+        ctx = _ctx(grid, n, h, tau, bc, tbs.PREC_FP32)
+        ctx.set_opts(fused_cg=fused)
+        ctx.ensure_workspace(tbs.PREC_FP32)
+        x = dev(np.zeros(grid[::-1]), "f32")
+        ctx.cg_begin(dev(b, "f32"), x, 0.0)
+        assert ctx.cg_step(k)[1] == k
+        xs.append(host(x))
+    xr, _, _ = solvers.cg(lambda v: op.apply(v, n, h, tau, bc), b, np.zeros_like(b), 0.0, 100, fixed_iters=k)
+    assert np.linalg.norm(xs[0] - xr) <= 1e-4 * np.linalg.norm(xr)
+    assert np.linalg.norm(xs[0] - xs[1]) <= 1e-4 * np.linalg.norm(xr)
 
 
 def test_config1_fp64_step_matches_fft_exact_and_conserves():
