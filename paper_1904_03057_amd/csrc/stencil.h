@@ -13,7 +13,7 @@
 #define STENCIL_CG_TY 16
 #endif
 #ifndef STENCIL_CGF_TY
-#define STENCIL_CGF_TY 32
+#define STENCIL_CGF_TY 48
 #endif
 #ifndef STENCIL_CG_PF
 #define STENCIL_CG_PF 1
@@ -47,18 +47,21 @@ constexpr int cgf_lds_bytes(int n, int ty, int bc) {
          (bc == BC_ROBIN ? 4 * (4 * kRobinMaxZ * kRobinMaxZ + (2 * (n / 2) + 1) * ty * 64) : 8);
 }
 
+// The one-kernel FP32 CG iteration's tile height: the tallest of STENCIL_CGF_TY, 32 and 16 rows
+// whose LDS fits one workgroup (row waves of four rows each: the registers per thread do not grow
+// with the height, and a taller tile re-reads fewer halo rows of r, q and p).
+constexpr int cgf_tile_y(int n, int bc) {
+  return cgf_lds_bytes(n, STENCIL_CGF_TY, bc) <= kLdsMax ? STENCIL_CGF_TY
+                                                          : (cgf_lds_bytes(n, 32, bc) <= kLdsMax ? 32 : 16);
+}
+
 // Tile height per (mode, compute precision, degree, boundary): taller tiles re-read fewer halo
 // rows.  The FP64 kernels take 16 rows in eight row waves of two rows (the FP64 ring and column
-// windows of two rows leave room for more waves per SIMD than four rows in four waves).  The
-// one-kernel FP32 CG iteration takes 32 rows (eight row waves of four rows: the same registers per
-// thread as 16 rows in four waves) wherever its LDS fits one workgroup, else 16.
+// windows of two rows leave room for more waves per SIMD than four rows in four waves).
 constexpr int stencil_tile_y(int mode, int compute_bytes, int n, int bc) {
   return compute_bytes == 4
              ? ((mode == M_APPLY) ? 32
-                                  : (mode == M_CG1 ? STENCIL_CG_TY
-                                                   : (mode == M_CGF ? (cgf_lds_bytes(n, STENCIL_CGF_TY, bc) <= kLdsMax
-                                                                           ? STENCIL_CGF_TY : 16)
-                                                                    : 16)))
+                                  : (mode == M_CG1 ? STENCIL_CG_TY : (mode == M_CGF ? cgf_tile_y(n, bc) : 16)))
              : (mode == M_RESID ? STENCIL_RESID_TY : 16);
 }
 // Row waves per workgroup: four for the FP32 kernels, except the one-kernel CG iteration, whose
