@@ -30,6 +30,7 @@ WEIGHTS = os.path.join(ROOT, "paper_1904_03057_amd", "weights", "guess_net_928z"
 
 # solver variants: (precision, use the network, tbs_opts.guess_backoff, tbs_opts.guess_test)
 SOLVERS = {
+    "learned_cost": ("mixed", True, 2, 0),       # refined FP32 + learned guess (residual test), cost-aware backoff
     "learned_backoff": ("mixed", True, 1, 0),    # refined FP32 + learned guess (residual test), backoff
     "learned_every": ("mixed", True, 0, 0),      # same, network run and judged on every step
     "learned_energy_backoff": ("mixed", True, 1, 1),  # energy test (A-norm-optimal multiple), backoff
@@ -37,7 +38,8 @@ SOLVERS = {
     "refined": ("mixed", False, 0, 0),           # refined FP32, plain guess
     "fp64": ("fp64", False, 0, 0),               # plain FP64 CG
 }
-SOLVER_NAMES = {"learned_backoff": "fp64-refined fp32 CG + learned guess (residual test, backoff)",
+SOLVER_NAMES = {"learned_cost": "fp64-refined fp32 CG + learned guess (residual test, cost-aware backoff)",
+                "learned_backoff": "fp64-refined fp32 CG + learned guess (residual test, backoff)",
                 "learned_every": "fp64-refined fp32 CG + learned guess (residual test, every step)",
                 "learned_energy_backoff": "fp64-refined fp32 CG + learned guess (energy test, backoff)",
                 "learned_energy_every": "fp64-refined fp32 CG + learned guess (energy test, every step)",
@@ -56,7 +58,7 @@ def main():
     ap.add_argument("--workload", default="heat928")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the timed steps (for profiling runs)")
-    ap.add_argument("--solver", default="learned_backoff", choices=list(SOLVERS),
+    ap.add_argument("--solver", default="learned_cost", choices=list(SOLVERS),
                     help="solver of the timed steps (the others are timed over the same steps in the extras)")
     ap.add_argument("--probe", default=None,
                     help="run one kernel kind --steps times for counter collection instead of the benchmark: "
@@ -420,6 +422,10 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N, k_all):
             ra[name]["net_kept"] = sum(s["used_learned_guess"] for s in sts)
             ra[name]["gamma_first"] = round(sts[0]["learned_gamma"], 4)
             ra[name]["iters_first_steps"] = [s["iters"] for s in sts[:5]]
+            if backoff == 2:
+                ran = [s for s in sts if not s["skipped_learned_guess"]]
+                ra[name]["saved_vs_cost_iters"] = [[round(s["learned_saved_iters"], 2), round(s["learned_cost_iters"], 2)]
+                                                   for s in ran]
         log("%d steps %s: %s" % (k_all, name, ra[name]))
     ctx.set_opts(poll_every=1)
     ctx.ensure_workspace(tbs.PREC_MIXED)

@@ -76,6 +76,11 @@ typedef struct {
   int skipped_learned_guess;  /* 1 if a network was passed but not run this step (guess_backoff) */
   double learned_gamma;    /* multiplier of the network output in the guess u^k + gamma du (energy
                               test: the A-norm-optimal one; residual test: 1; 0 if not run) */
+  double learned_saved_iters;  /* guess_backoff 2, kept guess: CG iterations it saved, estimated as
+                              ln(rel_res_learned / rel_res_plain) / ln(rho), rho the solve's mean
+                              residual reduction per iteration; 0 otherwise */
+  double learned_cost_iters;   /* guess_backoff 2, network run: the time of the network and its test
+                              in units of this step's time per CG iteration; 0 otherwise */
 } tbs_stats;
 
 typedef struct {
@@ -111,7 +116,12 @@ typedef struct {
   int guess_backoff;       /* tbs_timestep with a network: 0 = run and test the network guess on
                               every step (default); 1 = after the k-th consecutive rejection, skip
                               the network for the next min(2^(k-1), 64) steps (plain guess, no
-                              network cost), then test it again; a kept guess resets k.  The
+                              network cost), then test it again; a kept guess resets k.  2 = cost
+                              aware: as 1, but a kept guess resets k only if the iterations it
+                              saved (learned_saved_iters) took longer than the network and its test
+                              (learned_cost_iters, both timed with events on the stream); otherwise
+                              it counts as a rejection and the wait is at least the number of such
+                              steps it would take to pay once, min(64, cost / saving).  The
                               counters live in the context; tbs_set_opts resets them. */
   int guess_test;          /* how tbs_timestep judges the network output du (not in the paper):
                               0 = residual test (default): u^k + du is kept if its FP64 residual is

@@ -48,7 +48,8 @@ class Stats(ctypes.Structure):
                 ("rel_res_plain", ctypes.c_double), ("rel_res_learned", ctypes.c_double),
                 ("used_coarse_guess", ctypes.c_int), ("coarse_iters", ctypes.c_int),
                 ("rel_res_coarse", ctypes.c_double), ("skipped_learned_guess", ctypes.c_int),
-                ("learned_gamma", ctypes.c_double)]
+                ("learned_gamma", ctypes.c_double), ("learned_saved_iters", ctypes.c_double),
+                ("learned_cost_iters", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -164,6 +164,8 @@ struct tbs_ctx {
   int64_t cgrid[3];
   // learned-guess backoff (opts.guess_backoff): consecutive rejections, steps left to skip
   int guess_rejects, guess_wait;
+  hipEvent_t cost_ev[4];  // guess_backoff 2: network + test start / end, solve start / end
+  bool cost_ev_made;
   int cgf_pend;  // host copy of the pending x-update count of the one-kernel CG (for its byte count)
   // CG session state (tbs_cg_begin / tbs_cg_step)
   int cg_active, cg_dt, cg_enq;
@@ -359,6 +361,8 @@ extern "C" void tbs_destroy(tbs_ctx* c) {
   if (c->host_scal) (void)hipHostFree(c->host_scal);
   for (auto& r : c->prof_pending) { (void)hipEventDestroy(r.e0); (void)hipEventDestroy(r.e1); }
   for (auto e : c->prof_pool) (void)hipEventDestroy(e);
+  if (c->cost_ev_made)
+    for (auto e : c->cost_ev) (void)hipEventDestroy(e);
   delete c;
 }
 
@@ -462,7 +466,7 @@ extern "C" int tbs_set_opts(tbs_ctx* c, const tbs_opts* o) {
     if (!(o->inner_rtol > 0 && o->inner_rtol < 1) || o->inner_max_iter < 1 || o->max_sweeps < 1 ||
         o->poll_every < 1 || o->zchunk < 0 || o->tile_order < 0 || o->tile_order > 1 || o->nt_store < 0 ||
         o->nt_store > 1 || o->fused_cg < 0 || o->fused_cg > 1 || o->coarse_guess < 0 || o->coarse_guess > 1 ||
-        !(o->coarse_rtol > 0 && o->coarse_rtol < 1) || o->guess_backoff < 0 || o->guess_backoff > 1 ||
+        !(o->coarse_rtol > 0 && o->coarse_rtol < 1) || o->guess_backoff < 0 || o->guess_backoff > 2 ||
         o->guess_test < 0 || o->guess_test > 1)
       return set_err(TBS_E_INVAL, "bad options");
     if (o->coarse_guess) {
@@ -990,6 +994,20 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     g = nullptr;
     st.skipped_learned_guess = 1;
   }
+  // cost-aware backoff: events around the network and its test, and around the rest of the step
+  const bool costed = g && c->opts.guess_backoff == 2;
+  if (costed) {
+    if (!c->cost_ev_made) {
+      int made = 0;
+      while (made < 4 && hipEventCreate(&c->cost_ev[made]) == hipSuccess) ++made;
+      if (made < 4) {
+        while (made > 0) (void)hipEventDestroy(c->cost_ev[--made]);
+        return set_err(TBS_E_HIP, "hipEventCreate failed");
+      }
+      c->cost_ev_made = true;
+    }
+    HIPCHK(hipEventRecord(c->cost_ev[0], c->st));
+  }
 
   // initial guess: plain u^k, or the network guess if its FP64 residual is smaller.  The current
   // iterate is u_next once have_x is set, else u_prev itself: u_next is only written when a guess
@@ -1068,6 +1086,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
       }
     }
   }
+  if (costed) HIPCHK(hipEventRecord(c->cost_ev[1], c->st));
 
   if (!g && c->coarse && c->opts.coarse_guess && prec != TBS_PREC_FP32) {
     // coarse-grid guess: u_next = u_prev + P d, A_c d = P^T (b - A u_prev) / 8
@@ -1250,13 +1269,38 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
   if (g) {
     // backoff bookkeeping: a rejected guess counts, and so (energy test) does a kept one that did not
     // halve the plain guess's residual: it cannot save the iterations its network costs
-    const bool paid = st.used_learned_guess &&
-                      (c->opts.guess_test == 0 || st.rel_res_learned <= 0.5 * st.rel_res_plain);
+    bool paid = st.used_learned_guess &&
+                (c->opts.guess_test == 0 || st.rel_res_learned <= 0.5 * st.rel_res_plain);
+    int wait = 0;
+    if (costed) {
+      // cost-aware: the kept guess saved ln(learned / plain) / ln(rho) iterations, rho the solve's mean
+      // residual reduction per iteration; it paid if they took longer than the network and its test
+      HIPCHK(hipEventRecord(c->cost_ev[2], c->st));
+      HIPCHK(hipEventSynchronize(c->cost_ev[2]));
+      float t_guess = 0.f, t_solve = 0.f;
+      HIPCHK(hipEventElapsedTime(&t_guess, c->cost_ev[0], c->cost_ev[1]));
+      HIPCHK(hipEventElapsedTime(&t_solve, c->cost_ev[1], c->cost_ev[2]));
+      const double t_iter = st.iters > 0 ? (double)t_solve / st.iters : 0.0;
+      st.learned_cost_iters = t_iter > 0.0 ? t_guess / t_iter : 0.0;
+      double saved = 0.0;
+      if (st.used_learned_guess && st.iters > 0 && st.rel_res0 > 0.0 && st.rel_res_fp64 > 0.0 &&
+          st.rel_res_fp64 < st.rel_res0 && st.rel_res_learned > 0.0 && st.rel_res_plain > 0.0) {
+        const double log_rho = std::log(st.rel_res_fp64 / st.rel_res0) / st.iters;
+        saved = std::max(0.0, std::log(st.rel_res_learned / st.rel_res_plain) / log_rho);
+      }
+      st.learned_saved_iters = saved;
+      paid = paid && t_iter > 0.0 && saved >= st.learned_cost_iters;
+      if (!paid) {
+        // at least as many steps as such a guess would need to pay once
+        const double steps = saved > 0.0 ? std::ceil(st.learned_cost_iters / saved) : 64.0;
+        wait = (int)std::min(64.0, std::max(1.0, steps));
+      }
+    }
     if (paid) {
       c->guess_rejects = 0;
     } else {
       ++c->guess_rejects;
-      if (c->opts.guess_backoff) c->guess_wait = 1 << std::min(c->guess_rejects - 1, 6);
+      if (c->opts.guess_backoff) c->guess_wait = std::max(wait, 1 << std::min(c->guess_rejects - 1, 6));
     }
   }
   st.status = result;

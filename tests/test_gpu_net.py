@@ -240,6 +240,65 @@ def test_guess_backoff_skips_a_rejected_net():
         assert s["skipped_learned_guess"] == 0 and not np.isnan(s["rel_res_learned"])
 
 
+def test_cost_aware_backoff_rejected_net_waits_64_steps():
+    # guess_backoff = 2: a rejected guess saved nothing, so the network waits the cap of 64 steps
+    grid, n, tau = (32, 24, 20), 3, 1e-3
+    h = tuple(1.0 / (N + 1) for N in grid)
+    u = dev(normal_field(grid[::-1], 3))
+    theta = cnn_init(1)
+    theta[cnn.N_PARAMS - 1] = 100.0
+    net = tbs.Net()
+    net.ensure_workspace(grid, 1, False)
+    net.set_weights(theta)
+    ctx = tbs.Context(grid, n, h, tau, "dirichlet")
+    ctx.set_opts(guess_backoff=2)
+    ctx.ensure_workspace(tbs.PREC_MIXED)
+    a = dev(np.zeros(grid[::-1]))
+    s = ctx.timestep(u, None, a, tbs.PREC_MIXED, 1e-8, 500, net)
+    assert s["used_learned_guess"] == 0 and s["skipped_learned_guess"] == 0
+    assert s["learned_saved_iters"] == 0.0 and s["learned_cost_iters"] > 0.0
+    for _ in range(6):
+        s = ctx.timestep(u, None, a, tbs.PREC_MIXED, 1e-8, 500, net)
+        assert s["skipped_learned_guess"] == 1 and s["learned_cost_iters"] == 0.0
+
+
+def test_cost_aware_backoff_kept_guess_pays_or_waits():
+    # the trained 128^3 network's guess is kept on a held-out step; the library's estimate of the
+    # iterations it saved is ln(learned / plain) / ln(rho), rho the solve's mean residual reduction
+    # per iteration (recomputed here from the returned residuals), and the network runs on the next
+    # step exactly when that saving outweighed its cost, else it waits ceil(cost / saving) steps
+    import json
+    import os
+    from workloads import gaussian_params, gaussian_sum
+    wdir = os.path.join(os.path.dirname(tbs.__file__), "weights")
+    meta = json.load(open(os.path.join(wdir, "guess_net_128.json")))
+    grid, n, tau, rtol = tuple(meta["grid"]), 3, meta["tau"], 1e-8
+    h = (meta["h"],) * 3
+    L = (grid[0] + 1) * h[0]
+    u = dev(gaussian_sum(grid, "dirichlet", h, gaussian_params(9001, 16, 0.02, 0.1, 1.0, 0.1 * L, 0.9 * L)))
+    q = dev(gaussian_sum(grid, "dirichlet", h, gaussian_params(9002, 2, 0.05, 0.15, 10.0, 0.1 * L, 0.9 * L)))
+    net = tbs.Net()
+    net.ensure_workspace(grid, 1, False)
+    net.set_weights(np.fromfile(os.path.join(wdir, "guess_net_128.f32"), dtype="<f4"))
+    net.set_hparams(out_scale=meta["out_scale"])
+    ctx = tbs.Context(grid, n, h, tau, "dirichlet")
+    ctx.set_opts(guess_backoff=2)
+    ctx.ensure_workspace(tbs.PREC_MIXED)
+    un = torch.empty_like(u)
+    s = ctx.timestep(u, q, un, tbs.PREC_MIXED, rtol, 2000, net)
+    assert s["converged"] and s["used_learned_guess"] == 1, s
+    log_rho = np.log(s["rel_res_fp64"] / s["rel_res0"]) / s["iters"]
+    saved = max(0.0, np.log(s["rel_res_learned"] / s["rel_res_plain"]) / log_rho)
+    assert saved > 0.0 and abs(s["learned_saved_iters"] - saved) <= 1e-9 * saved
+    cost = s["learned_cost_iters"]
+    assert cost > 0.0
+    wait = 0 if saved >= cost else min(64, max(1, int(np.ceil(cost / saved))))
+    skips = []
+    for _ in range(min(wait, 4) + 1):
+        skips.append(ctx.timestep(u, q, un, tbs.PREC_MIXED, rtol, 2000, net)["skipped_learned_guess"])
+    assert skips == [1] * min(wait, 4) + ([0] if wait <= 4 else [1]), (saved, cost, skips)
+
+
 def test_adam_over_several_steps_matches_oracle():
     # four training steps; after each the device's own gradient drives the oracle's Adam (pinned by
     # the constant-gradient closed form for every t), whose weights must equal the device's: this
