@@ -102,7 +102,8 @@ typedef struct {
                               the explicit r.r, beta and the stopping test from the one-step
                               prediction r.r - 2 alpha r.q + alpha^2 q.q; 0 = the two-kernel
                               Hestenes-Stiefel iteration (q = A p and p.q, then r -= alpha q and r.r).
-                              The FP64 CG always uses the two-kernel form. */
+                              Applies to the FP64 CG too (TBS_PREC_FP64, tbs_cg_step in F64,
+                              tbs_transform_interp and the coarse-grid solve). */
   int coarse_guess;        /* 1: tbs_timestep without a network starts from a coarse-grid guess
                               (Sec. 3 leg example: CG started from a reduced-grid solution): the
                               residual of u_prev is restricted to the halved grid, the coarse
@@ -344,8 +345,9 @@ int tbs_net_get_grad(const tbs_net* net, float* host, size_t n);
  * Kinds: 0 apply f64, 1 apply f32, 2 apply bf16->f32, 3 rhs f64, 4 rhs f32, 5 cg-fused f64,
  * 6 cg-fused f32, 7 cg-fused f32 with bf16 p, 8 residual f64, 9 cg-update f64, 10 cg-update f32,
  * 11 one-kernel CG iteration f32, 12 one-kernel CG iteration f32 with bf16 p, 13 variable-coefficient
- * apply f64, 14 variable-coefficient apply f32 (bytes: u, d, m read and y written once). */
-#define TBS_PROF_KINDS 15
+ * apply f64, 14 variable-coefficient apply f32 (bytes: u, d, m read and y written once), 15 one-kernel
+ * CG iteration f64. */
+#define TBS_PROF_KINDS 16
 int tbs_prof_enable(tbs_ctx* ctx, int on);   /* resets the counters */
 int tbs_prof_read(tbs_ctx* ctx, int kind, double* total_ms, double* total_bytes, int64_t* launches);
 

@@ -39,7 +39,7 @@ EXPORTS = [
 ]
 PROF_KINDS = ["apply_f64", "apply_f32", "apply_bf16_f32", "rhs_f64", "rhs_f32", "cg_fused_f64", "cg_fused_f32",
               "cg_fused_f32_bf16p", "residual_f64", "cg_update_f64", "cg_update_f32", "cg_iter_f32",
-              "cg_iter_f32_bf16p", "varcoef_f64", "varcoef_f32"]
+              "cg_iter_f32_bf16p", "varcoef_f64", "varcoef_f32", "cg_iter_f64"]
 
 
 class Stats(ctypes.Structure):

@@ -222,8 +222,8 @@ static Layout layout(const tbs_ctx* c, int prec) {
   auto put = [&](int i, size_t esz) { L.off[i] = o; o += align256(N * esz); };
   switch (prec) {
     case -1: break;
-    case TBS_PREC_FP64:  // b, r, pA, pB, q
-      put(0, 8); put(1, 8); put(2, 8); put(3, 8); put(4, 8); break;
+    case TBS_PREC_FP64:  // b, r, pA, pB, q, rB, qB (rB, qB: second r, q of the one-kernel iteration)
+      put(0, 8); put(1, 8); put(2, 8); put(3, 8); put(4, 8); put(5, 8); put(6, 8); break;
     case TBS_PREC_FP32:  // b, x, r, pA, pB, q, rB, qB (f32; rB, qB: second r, q of the one-kernel iteration)
       put(0, 4); put(1, 4); put(2, 4); put(3, 4); put(4, 4); put(5, 4); put(6, 4); put(7, 4); break;
     case TBS_PREC_MIXED:  // b64, r32, d, pA, pB, q, rB, qB
@@ -776,7 +776,7 @@ static int cg1_async(tbs_ctx* c, const CgArrays& A, int dt, int k) {
   return TBS_OK;
 }
 
-// One-kernel CG iteration k (FP32 vectors): r_k = r_{k-1} - alpha q_{k-1}, p_k = r_k + beta p_{k-1},
+// One-kernel CG iteration k (dt 0: FP64, 1: FP32, 2: FP32 with bf16 p): r_k = r_{k-1} - alpha q_{k-1}, p_k = r_k + beta p_{k-1},
 // q_k = A p_k and the FP64 partial sums of p.q, r.q, q.q and r.r in one stencil launch, then one
 // reduction; every second iteration also x += alpha2 p_{k-2} + alpha p_{k-1} (the two pending
 // updates).  r, p and q alternate between two arrays (halo reads of the old values and writes of
@@ -794,17 +794,17 @@ static int cgf_async(tbs_ctx* c, const CgArrays& A, int dt, int k) {
   a.io0 = A.x;
   a.scal = scal(c, SC_CG);
   a.first = (k == 0);
-  const double tp = dt == 1 ? 4 : 2;
+  const double tc = dt == 0 ? 8 : 4, tp = dt == 0 ? 8 : (dt == 1 ? 4 : 2);
   // first iteration: read r, write r, p, q; later: read r, q, p_old, write r, p, q, and on the
   // iterations that advance x also read x, p_{k-2} and write x
   const int pend = k == 0 ? 0 : c->cgf_pend;
-  const double b1 = (double)c->N * (k == 0 ? (12 + tp) : (pend == 2 ? 24 + 3 * tp : 2 * (8 + tp)));
+  const double b1 = (double)c->N * (k == 0 ? 3 * tc + tp : (pend == 2 ? 6 * tc + 3 * tp : 2 * (2 * tc + tp)));
   c->cgf_pend = (pend == 2 ? 0 : pend) + 1;
-  int ps = prof_begin(c, dt == 1 ? 11 : 12, k, b1);
+  int ps = prof_begin(c, dt == 0 ? 15 : (dt == 1 ? 11 : 12), k, b1);
   HIPCHK(launch_cgf(a, c->n, c->bc, dt, c->st));
   prof_end(c, ps);
-  HIPCHK(launch_finalize(FIN_FUSED, part0(c), part1(c), stencil_blocks(a, M_CGF, 4, c->n, c->bc), scal(c, SC_CG), 0.0, c->st,
-                         part2(c), part3(c)));
+  HIPCHK(launch_finalize(FIN_FUSED, part0(c), part1(c), stencil_blocks(a, M_CGF, (int)tc, c->n, c->bc), scal(c, SC_CG),
+                         0.0, c->st, part2(c), part3(c)));
   return TBS_OK;
 }
 
@@ -819,7 +819,7 @@ static int cg_loop(tbs_ctx* c, const CgArrays& A, int dt, int k0, int max_iter, 
   while (!s.done && k < max_iter) {
     const int batch = std::min(c->opts.poll_every, max_iter - k);
     for (int i = 0; i < batch; ++i) {
-      rc = (dt != 0 && c->opts.fused_cg) ? cgf_async(c, A, dt, k++) : cg1_async(c, A, dt, k++);
+      rc = c->opts.fused_cg ? cgf_async(c, A, dt, k++) : cg1_async(c, A, dt, k++);
       if (rc) return rc;
     }
     rc = read_scal(c, SC_CG, &s);
@@ -863,8 +863,10 @@ extern "C" int tbs_cg_begin(tbs_ctx* c, const void* b, void* x, int dt, double r
   CgArrays A;
   A.x = x;
   A.r2 = A.q2 = nullptr;
-  if (dt == TBS_F64) { A.r = c->ws + L.off[1]; A.p[0] = c->ws + L.off[2]; A.p[1] = c->ws + L.off[3]; A.q = c->ws + L.off[4]; }
-  else {
+  if (dt == TBS_F64) {
+    A.r = c->ws + L.off[1]; A.p[0] = c->ws + L.off[2]; A.p[1] = c->ws + L.off[3]; A.q = c->ws + L.off[4];
+    A.r2 = c->ws + L.off[5]; A.q2 = c->ws + L.off[6];
+  } else {
     A.r = c->ws + L.off[2]; A.p[0] = c->ws + L.off[3]; A.p[1] = c->ws + L.off[4]; A.q = c->ws + L.off[5];
     A.r2 = c->ws + L.off[6]; A.q2 = c->ws + L.off[7];
   }
@@ -888,8 +890,10 @@ extern "C" int tbs_cg_step(tbs_ctx* c, int n_iters, double* rel_res_out, int* it
   CgArrays A;
   A.x = c->cg_x;
   A.r2 = A.q2 = nullptr;
-  if (c->cg_dt == TBS_F64) { A.r = c->ws + L.off[1]; A.p[0] = c->ws + L.off[2]; A.p[1] = c->ws + L.off[3]; A.q = c->ws + L.off[4]; }
-  else {
+  if (c->cg_dt == TBS_F64) {
+    A.r = c->ws + L.off[1]; A.p[0] = c->ws + L.off[2]; A.p[1] = c->ws + L.off[3]; A.q = c->ws + L.off[4];
+    A.r2 = c->ws + L.off[5]; A.q2 = c->ws + L.off[6];
+  } else {
     A.r = c->ws + L.off[2]; A.p[0] = c->ws + L.off[3]; A.p[1] = c->ws + L.off[4]; A.q = c->ws + L.off[5];
     A.r2 = c->ws + L.off[6]; A.q2 = c->ws + L.off[7];
   }
@@ -930,7 +934,8 @@ extern "C" int tbs_transform_interp(tbs_ctx* c, const double* samples, double* c
   if (rc) return rc;
   c->cg_active = 0;
   const Layout L = layout(c, TBS_PREC_FP64);
-  CgArrays A{coef, c->ws + L.off[1], {c->ws + L.off[2], c->ws + L.off[3]}, c->ws + L.off[4], nullptr, nullptr};
+  CgArrays A{coef, c->ws + L.off[1], {c->ws + L.off[2], c->ws + L.off[3]}, c->ws + L.off[4], c->ws + L.off[5],
+             c->ws + L.off[6]};
   rc = cg_init_async(c, samples, A, 0, rtol);
   if (rc) return rc;
   int nit = 0;
@@ -1115,7 +1120,8 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     if (rc) return rc;
     HIPCHK(launch_fill(xc, 0, cc->N, c->st));
     const Layout Lc = layout(cc, TBS_PREC_FP64);
-    CgArrays Ac{xc, cc->ws + Lc.off[1], {cc->ws + Lc.off[2], cc->ws + Lc.off[3]}, cc->ws + Lc.off[4], nullptr, nullptr};
+    CgArrays Ac{xc, cc->ws + Lc.off[1], {cc->ws + Lc.off[2], cc->ws + Lc.off[3]}, cc->ws + Lc.off[4], cc->ws + Lc.off[5],
+                cc->ws + Lc.off[6]};
     rc = cg_init_async(cc, bcv, Ac, 0, c->opts.coarse_rtol);
     if (rc) return rc;
     int cit = 0;
@@ -1158,7 +1164,8 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
   if (prec == TBS_PREC_FP64) {
     rc = ensure_x();  // CG iterates in place on u_next
     if (rc) return rc;
-    CgArrays A{u_next, c->ws + L.off[1], {c->ws + L.off[2], c->ws + L.off[3]}, c->ws + L.off[4], nullptr, nullptr};
+    CgArrays A{u_next, c->ws + L.off[1], {c->ws + L.off[2], c->ws + L.off[3]}, c->ws + L.off[4], c->ws + L.off[5],
+               c->ws + L.off[6]};
     rc = cg_init_async(c, b64, A, 0, rtol);
     if (rc) return rc;
     Scalars s;

@@ -32,27 +32,34 @@ namespace tbs {
 
 constexpr int kTileX = 64;
 constexpr int imin(int a, int b) { return a < b ? a : b; }
-// smallest tile height of any stencil launch (the one-kernel FP32 CG iteration takes 16 rows or
-// more): sizes the partial-sum buffers
-constexpr int kTileY = imin(imin(STENCIL_RESID_TY, STENCIL_TY), imin(STENCIL_CG_TY, 16));
+// smallest tile height of any stencil launch (the one-kernel CG iteration takes 16 rows or more in
+// FP32, 8 or 16 in FP64): sizes the partial-sum buffers
+constexpr int kTileY = imin(imin(STENCIL_RESID_TY, STENCIL_TY), imin(STENCIL_CG_TY, 8));
 constexpr int kTileYPlan = 16;  // tile height the z-chunk plan assumes
 constexpr int kLdsMax = 160 * 1024;  // LDS one workgroup may hold on gfx950
 
-// LDS of the one-kernel FP32 CG iteration (degree n, tile height ty, 64 columns): staged plane
-// (x halo of at most 8 columns a side: one 16-byte vector of bf16), the two x-pass planes, the p
-// and r rings, the reduction slots, and the Robin corner tables and z-accumulators (one-element
-// placeholders otherwise).  An upper bound of what the kernel declares (it asserts so).
-constexpr int cgf_lds_bytes(int n, int ty, int bc) {
-  return 4 * ((ty + 2 * n) * (64 + 16) + 2 * (ty + 2 * n) * 64 + (2 * n + 3) * ty * 64) + 8 * 4 * (ty / 4) +
-         (bc == BC_ROBIN ? 4 * (4 * kRobinMaxZ * kRobinMaxZ + (2 * (n / 2) + 1) * ty * 64) : 8);
+// Rows per row wave of the one-kernel CG iteration: four in FP32, two in FP64.
+constexpr int cgf_rows_per_wave(int es) { return es == 4 ? 4 : 2; }
+
+// LDS of the one-kernel CG iteration (degree n, tile height ty, 64 columns, es-byte compute type):
+// staged plane (x halo of at most 8 columns a side: one 16-byte vector of bf16), the two x-pass
+// planes, the p and r rings, the reduction slots, and the Robin corner tables and z-accumulators
+// (one-element placeholders otherwise).  An upper bound of what the kernel declares (it asserts so).
+constexpr int cgf_lds_bytes(int n, int ty, int bc, int es) {
+  return es * ((ty + 2 * n) * (64 + 16) + 2 * (ty + 2 * n) * 64 + (2 * n + 3) * ty * 64) +
+         8 * 4 * (ty / cgf_rows_per_wave(es)) +
+         (bc == BC_ROBIN ? es * (4 * kRobinMaxZ * kRobinMaxZ + (2 * (n / 2) + 1) * ty * 64) : 2 * es);
 }
 
-// The one-kernel FP32 CG iteration's tile height: the tallest of STENCIL_CGF_TY, 32 and 16 rows
+// The one-kernel CG iteration's tile height: in FP32 the tallest of STENCIL_CGF_TY, 32 and 16 rows
 // whose LDS fits one workgroup (row waves of four rows each: the registers per thread do not grow
-// with the height, and a taller tile re-reads fewer halo rows of r, q and p).
-constexpr int cgf_tile_y(int n, int bc) {
-  return cgf_lds_bytes(n, STENCIL_CGF_TY, bc) <= kLdsMax ? STENCIL_CGF_TY
-                                                          : (cgf_lds_bytes(n, 32, bc) <= kLdsMax ? 32 : 16);
+// with the height, and a taller tile re-reads fewer halo rows of r, q and p); in FP64 16 rows, or 8
+// where 16 do not fit (Robin quartic and quintic).
+constexpr int cgf_tile_y(int n, int bc, int es) {
+  return es == 4 ? (cgf_lds_bytes(n, STENCIL_CGF_TY, bc, 4) <= kLdsMax
+                        ? STENCIL_CGF_TY
+                        : (cgf_lds_bytes(n, 32, bc, 4) <= kLdsMax ? 32 : 16))
+                 : (cgf_lds_bytes(n, 16, bc, 8) <= kLdsMax ? 16 : 8);
 }
 
 // Tile height per (mode, compute precision, degree, boundary): taller tiles re-read fewer halo
@@ -61,15 +68,14 @@ constexpr int cgf_tile_y(int n, int bc) {
 constexpr int stencil_tile_y(int mode, int compute_bytes, int n, int bc) {
   return compute_bytes == 4
              ? ((mode == M_APPLY) ? 32
-                                  : (mode == M_CG1 ? STENCIL_CG_TY : (mode == M_CGF ? cgf_tile_y(n, bc) : 16)))
-             : (mode == M_RESID ? STENCIL_RESID_TY : 16);
+                                  : (mode == M_CG1 ? STENCIL_CG_TY : (mode == M_CGF ? cgf_tile_y(n, bc, 4) : 16)))
+             : (mode == M_RESID ? STENCIL_RESID_TY : (mode == M_CGF ? cgf_tile_y(n, bc, 8) : 16));
 }
 // Row waves per workgroup: four for the FP32 kernels, except the one-kernel CG iteration, whose
-// waves keep four rows each; eight for the FP64 kernels.
+// waves keep four rows each (two in FP64); eight for the other FP64 kernels.
 constexpr int stencil_tile_wy(int mode, int compute_bytes, int n, int bc) {
-  return (mode == M_CGF && compute_bytes == 4) ? stencil_tile_y(mode, compute_bytes, n, bc) / 4
-                                               : (mode == M_RESID ? STENCIL_RESID_WY
-                                                                  : (compute_bytes == 8 ? STENCIL_F64_WY : 4));
+  return mode == M_CGF ? stencil_tile_y(mode, compute_bytes, n, bc) / cgf_rows_per_wave(compute_bytes)
+                       : (mode == M_RESID ? STENCIL_RESID_WY : (compute_bytes == 8 ? STENCIL_F64_WY : 4));
 }
 // One stencil launch of degree N for a (mode, input, compute, output) type combination and
 // boundary condition BC; defined in stencil_kernel.h and instantiated per degree and boundary

@@ -51,6 +51,7 @@ hipError_t launch_cg1(const StencilArgs& a, int n, int bc, int dt, hipStream_t s
 }
 
 hipError_t launch_cgf(const StencilArgs& a, int n, int bc, int dt, hipStream_t st) {
+  if (dt == 0) return launch_n<M_CGF, double, double, double>(a, n, bc, st);
   if (dt == 1) return launch_n<M_CGF, float, float, float>(a, n, bc, st);
   if (dt == 2) return launch_n<M_CGF, uint16_t, float, float>(a, n, bc, st);
   return hipErrorInvalidValue;

@@ -77,7 +77,7 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
   __shared__ Tc rbt[BC == BC_ROBIN ? 4 * RBT : 1];
   __shared__ Tc zl[BC == BC_ROBIN ? (2 * (N / 2) + 1) * TY * TX : 1];
   static_assert(sizeof(stage) + sizeof(su) + sizeof(sv) + sizeof(cring) + sizeof(rring) + sizeof(red) + sizeof(rbt) +
-                        sizeof(zl) <= (FUSED ? cgf_lds_bytes(N, TY, BC) : kLdsMax),
+                        sizeof(zl) <= (FUSED ? cgf_lds_bytes(N, TY, BC, (int)sizeof(Tc)) : kLdsMax),
                 "LDS of the workgroup");
 
   if (CG && a.scal->done) return;
@@ -581,6 +581,7 @@ hipError_t launch_bcx(const StencilArgs& a0, bool vec, hipStream_t st) {
   template hipError_t launch_bcx<N, M_CG1, double, double, double, BC>(const StencilArgs&, bool, hipStream_t);     \
   template hipError_t launch_bcx<N, M_CG1, float, float, float, BC>(const StencilArgs&, bool, hipStream_t);        \
   template hipError_t launch_bcx<N, M_CG1, uint16_t, float, float, BC>(const StencilArgs&, bool, hipStream_t);     \
+  template hipError_t launch_bcx<N, M_CGF, double, double, double, BC>(const StencilArgs&, bool, hipStream_t);     \
   template hipError_t launch_bcx<N, M_CGF, float, float, float, BC>(const StencilArgs&, bool, hipStream_t);        \
   template hipError_t launch_bcx<N, M_CGF, uint16_t, float, float, BC>(const StencilArgs&, bool, hipStream_t);     \
   template hipError_t launch_bcx<N, M_RESID, double, double, double, BC>(const StencilArgs&, bool, hipStream_t);   \

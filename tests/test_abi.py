@@ -47,7 +47,7 @@ def test_valid_setup_and_workspace_sizes_without_gpu():
     base = lib.tbs_workspace_bytes(p, -1)
     N = 33 * 17 * 9
     assert base > 0
-    assert lib.tbs_workspace_bytes(p, tbs.PREC_FP64) >= base + 5 * N * 8
+    assert lib.tbs_workspace_bytes(p, tbs.PREC_FP64) >= base + 7 * N * 8
     assert lib.tbs_workspace_bytes(p, tbs.PREC_MIXED) >= base + N * 8 + 5 * N * 4
     assert lib.tbs_workspace_bytes(p, 9) == 0
     m = (ctypes.c_double * 3)()

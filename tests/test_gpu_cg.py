@@ -26,11 +26,15 @@ def config1_fields():
 
 @pytest.mark.parametrize("bc,grid", [("dirichlet", (40, 24, 18)), ("periodic", (32, 20, 16))])
 @pytest.mark.parametrize("k", [1, 3, 12])
-def test_cg_iterate_parity_fp64(bc, grid, k):
+@pytest.mark.parametrize("fused", [1, 0])
+def test_cg_iterate_parity_fp64(bc, grid, k, fused):
+    # both FP64 iteration forms (one kernel with the r.r prediction, two kernels) against the
+    # oracle's Hestenes-Stiefel iterates
     n, h, tau = 3, (1 / 40, 1 / 24, 1 / 18), 2e-3
     b = normal_field(grid[::-1], 11)
     x0 = normal_field(grid[::-1], 12) * 0.1
     ctx = _ctx(grid, n, h, tau, bc, tbs.PREC_FP64)
+    ctx.set_opts(fused_cg=fused)
     ctx.ensure_workspace(tbs.PREC_FP64)
     x = dev(x0)
     ctx.cg_begin(dev(b), x, 0.0)
@@ -42,10 +46,13 @@ def test_cg_iterate_parity_fp64(bc, grid, k):
     assert abs(rel - hist[-1]) <= 1e-8 * hist[-1]
 
 
-def test_cg_step_continuation_bitwise():
+@pytest.mark.parametrize("fused", [1, 0])
+def test_cg_step_continuation_bitwise(fused):
     grid, n, h, tau, bc = (33, 21, 17), 2, (0.03, 0.05, 0.06), 1e-3, "periodic"
     b = dev(normal_field(grid[::-1], 1))
     ctx = _ctx(grid, n, h, tau, bc, tbs.PREC_FP64)
+    ctx.set_opts(fused_cg=fused)
+    ctx.ensure_workspace(tbs.PREC_FP64)
     x1 = dev(np.zeros(grid[::-1]))
     ctx.cg_begin(b, x1, 0.0)
     ctx.cg_step(10)
@@ -132,9 +139,12 @@ def test_cg_fp32_one_kernel_x_after_k_iterations(k):
     assert np.linalg.norm(xs[0] - xs[1]) <= 1e-4 * np.linalg.norm(xr)
 
 
-def test_config1_fp64_step_matches_fft_exact_and_conserves():
+@pytest.mark.parametrize("fused", [1, 0])
+def test_config1_fp64_step_matches_fft_exact_and_conserves(fused):
     w, u0 = config1_fields()
     ctx = _ctx(w.grid, w.degree, w.h, w.tau, w.bc, tbs.PREC_FP64)
+    ctx.set_opts(fused_cg=fused)
+    ctx.ensure_workspace(tbs.PREC_FP64)
     un = dev(np.zeros(u0.shape))
     st = ctx.timestep(dev(u0), None, un, tbs.PREC_FP64, w.rtol, 500)
     assert st["converged"]
