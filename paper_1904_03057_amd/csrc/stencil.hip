@@ -1,5 +1,5 @@
-// Dispatch of the stencil launches: (mode, dtype) combinations and basis degree n -> the kernel
-// instances of stencil_kernel.h compiled per degree in stencil_n<k>.hip.
+// Dispatch of the stencil launches: (mode, dtype) combinations, basis degree n and boundary -> the
+// kernel instances of stencil_kernel.h that stencil_inst.hip compiles per degree and boundary.
 #include "common.h"
 #include "stencil.h"
 
