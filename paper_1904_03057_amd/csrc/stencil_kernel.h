@@ -99,7 +99,7 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
   const int lane = tid & 63;
   const int wv = tid >> 6;
   const int col = (wv % WX) * 64 + lane;           // tile column of this lane
-  const int wave = wv / WX;                        // row group 0..WY-1
+  const int wave = __builtin_amdgcn_readfirstlane(wv / WX);  // row group 0..WY-1 (wave-uniform)
 
   const int bid = xcd_remap(blockIdx.x, a.nblocks);
   // logical tile order (x- or y-tiles fastest, then the other, then z-chunks): the tiles an XCD
@@ -341,6 +341,7 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
             cring[(qs * TY + wave * RPW + i) * TX + col] = stage[(wave * RPW + i + N) * C + col + HX];
         }
         // x-pass over all R staged rows (rows dealt to the waves round-robin)
+#pragma unroll 2
         for (int r = wave; r < R; r += WY) {
           const Tc* row = stage + r * C + HX + col;
           const Tc c0 = row[0];
