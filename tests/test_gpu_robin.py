@@ -150,6 +150,29 @@ def test_robin_cg_reduces_the_residual_at_higher_degree(n):
     assert abs(true_rel - rel) <= 1e-3 * rel0
 
 
+@pytest.mark.parametrize("n", [4, 5])
+@pytest.mark.parametrize("fused", [1, 0])
+def test_robin_fp64_cg_iterates_at_degrees_4_and_5(n, fused):
+    # quartic / quintic box: the one-kernel FP64 iteration falls back to 8-row tiles there (the
+    # 16-row one would not fit its LDS); its first iterates and residual history against the
+    # oracle's Hestenes-Stiefel CG on the Robin operator, and against the two-kernel form
+    from oracle import solvers
+    grid, tau, gamma, k = (21, 19, 18), 1e-3, 0.05, 4
+    h = box_h(grid, n)
+    ctx = tbs.RobinContext(grid, n, h, tau, gamma)
+    ctx.set_opts(fused_cg=fused)
+    ctx.ensure_workspace(tbs.PREC_FP64)
+    x0 = normal_field(grid[::-1], 31) * 0.1
+    b = normal_field(grid[::-1], 32)
+    x = dev(x0)
+    ctx.cg_begin(dev(b), x, 0.0)
+    rel, it = ctx.cg_step(k)
+    xr, _, hist = solvers.cg(lambda v: robin.apply(v, n, h, tau, gamma), b, x0, 0.0, 100, fixed_iters=k)
+    assert it == k
+    assert np.linalg.norm(host(x) - xr) <= 1e-9 * np.linalg.norm(xr)
+    assert abs(rel - hist[-1]) <= 1e-7 * hist[-1]
+
+
 def test_robin_apply_928_sampled():
     n, N, tau, gamma = 3, 928, 1e-5, 1e-3
     grid = (N, N, N)
