@@ -99,7 +99,7 @@ def main():
         ctx = tbs.Context(w.grid, w.degree, w.h, w.tau, w.bc, stream=stream)
         # poll convergence after every CG iteration: no launch ever runs past convergence, so the
         # profiler's per-launch averages and rocprofv3's agree (one 8-byte read per ~ms iteration)
-        ctx.set_opts(poll_every=1)
+        ctx.set_opts()
         ctx.ensure_workspace(tbs.PREC_MIXED)
     net = None
     if os.path.exists(WEIGHTS + ".f32") and args.workload == "heat928":
@@ -113,7 +113,7 @@ def main():
     if suse and net is None:
         raise SystemExit("solver %s needs the trained weights %s.f32" % (args.solver, WEIGHTS))
     PREC = tbs.PREC_MIXED if sprec == "mixed" else tbs.PREC_FP64
-    ctx.set_opts(poll_every=1, guess_backoff=sbackoff, guess_test=stest)
+    ctx.set_opts(guess_backoff=sbackoff, guess_test=stest)
     ctx.ensure_workspace(PREC)
 
     def step(prec, use_net):
@@ -128,7 +128,7 @@ def main():
     torch.cuda.synchronize()
     ua.copy_(u0)
     # the backoff counters restart with the timed steps
-    ctx.set_opts(poll_every=1, guess_backoff=sbackoff, guess_test=stest)
+    ctx.set_opts(guess_backoff=sbackoff, guess_test=stest)
     ctx.ensure_workspace(PREC)
     torch.cuda.synchronize()
 
@@ -383,7 +383,7 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N, k_all):
         variants.append(("refined_fp32_learned", tbs.PREC_MIXED, True))
     ctx.ensure_workspace(tbs.PREC_FP64)
     for name, prec, use_net in variants:
-        ctx.set_opts(poll_every=1)
+        ctx.set_opts()
         ctx.ensure_workspace(tbs.PREC_FP64)
         t, sts = time_steps(prec, use_net, 2)
         sp[name] = {"s_per_step": round(t, 4), "iters": [s["iters"] for s in sts],
@@ -391,7 +391,7 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N, k_all):
                     "learned_used": [s["used_learned_guess"] for s in sts]}
         log("%s: %s" % (name, sp[name]))
     # the paper's reduced-grid start: coarse-grid guess (halved grid, two-scale prolongation)
-    ctx.set_opts(poll_every=1, coarse_guess=1, coarse_rtol=1e-2)
+    ctx.set_opts(coarse_guess=1, coarse_rtol=1e-2)
     for name, prec in (("refined_fp32_coarse", tbs.PREC_MIXED), ("plain_fp64_cg_coarse", tbs.PREC_FP64)):
         ctx.ensure_workspace(prec)
         t, sts = time_steps(prec, False, 2)
@@ -401,7 +401,7 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N, k_all):
                     "coarse_iters": [s["coarse_iters"] for s in sts],
                     "coarse_over_plain_residual": [round(s["rel_res_coarse"] / s["rel_res_plain"], 4) for s in sts]}
         log("%s: %s" % (name, sp[name]))
-    ctx.set_opts(poll_every=1)
+    ctx.set_opts()
     res["s_per_step"] = sp
     # every solver variant over the same k_all steps as the timed run, from the same field
     ra = {}
@@ -409,7 +409,7 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N, k_all):
         if use_net and net is None:
             continue
         prec = tbs.PREC_MIXED if prec_s == "mixed" else tbs.PREC_FP64
-        ctx.set_opts(poll_every=1, guess_backoff=backoff, guess_test=test)
+        ctx.set_opts(guess_backoff=backoff, guess_test=test)
         ctx.ensure_workspace(tbs.PREC_FP64)
         t, sts = time_steps(prec, use_net, k_all)
         name = {"fp64": "plain_fp64_cg", "refined": "refined_fp32"}.get(key, "refined_fp32_" + key)
@@ -427,7 +427,7 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N, k_all):
                 ra[name]["saved_vs_cost_iters"] = [[round(s["learned_saved_iters"], 2), round(s["learned_cost_iters"], 2)]
                                                    for s in ran]
         log("%d steps %s: %s" % (k_all, name, ra[name]))
-    ctx.set_opts(poll_every=1)
+    ctx.set_opts()
     ctx.ensure_workspace(tbs.PREC_MIXED)
     res["all_%d_steps" % k_all] = ra
     if net is not None:
@@ -522,7 +522,7 @@ def robin_box(tbs, torch, w):
                               "frac_hbm": round(by / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
         del y
     for name, prec in (("refined_fp32", tbs.PREC_MIXED), ("plain_fp64_cg", tbs.PREC_FP64)):
-        ctx.set_opts(poll_every=1)
+        ctx.set_opts()
         ctx.ensure_workspace(tbs.PREC_FP64)
         ua, ub = u.clone(), torch.empty_like(u)
         torch.cuda.synchronize()
@@ -584,7 +584,7 @@ def workload_steps(tbs, torch):
     out = {}
     w = workloads.HEAT_256_DIRICHLET
     ctx = tbs.Context(w.grid, w.degree, w.h, w.tau, w.bc)
-    ctx.set_opts(poll_every=1)
+    ctx.set_opts()
     u = torch.from_numpy(workloads.uniform_field(w.grid[::-1], w.seed)).cuda()
     t = torch.empty_like(u)
     for _ in range(w.smooth_passes):
@@ -618,7 +618,7 @@ def workload_steps(tbs, torch):
     r4 = {}
     for n in w.degrees:
         ctx = tbs.Context(w.grid, n, w.h, w.tau, w.bc)
-        ctx.set_opts(poll_every=1)
+        ctx.set_opts()
         ctx.ensure_workspace(tbs.PREC_MIXED)
         ua, ub = u0.clone(), torch.empty_like(u0)
         for _ in range(w.smooth_passes):
