@@ -122,7 +122,8 @@ typedef struct {
                               saved (learned_saved_iters) took longer than the network and its test
                               (learned_cost_iters, both timed with events on the stream); otherwise
                               it counts as a rejection and the wait is at least the number of such
-                              steps it would take to pay once, min(64, cost / saving).  The
+                              steps it would take to pay once, min(64, cost / saving); a kept guess
+                              that meets rtol without any iteration pays.  The
                               counters live in the context; tbs_set_opts resets them. */
   int guess_test;          /* how tbs_timestep judges the network output du (not in the paper):
                               0 = residual test (default): u^k + du is kept if its FP64 residual is

@@ -1296,7 +1296,9 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
         saved = std::max(0.0, std::log(st.rel_res_learned / st.rel_res_plain) / log_rho);
       }
       st.learned_saved_iters = saved;
-      paid = paid && t_iter > 0.0 && saved >= st.learned_cost_iters;
+      // a kept guess that left nothing to iterate paid in full
+      const bool solved = st.used_learned_guess && st.iters == 0 && result == TBS_OK;
+      paid = paid && (solved || (t_iter > 0.0 && saved >= st.learned_cost_iters));
       if (!paid) {
         // at least as many steps as such a guess would need to pay once
         const double steps = saved > 0.0 ? std::ceil(st.learned_cost_iters / saved) : 64.0;

@@ -297,6 +297,15 @@ def test_cost_aware_backoff_kept_guess_pays_or_waits():
     for _ in range(min(wait, 4) + 1):
         skips.append(ctx.timestep(u, q, un, tbs.PREC_MIXED, rtol, 2000, net)["skipped_learned_guess"])
     assert skips == [1] * min(wait, 4) + ([0] if wait <= 4 else [1]), (saved, cost, skips)
+    # a tolerance between the guess's residual and the plain one: the kept guess needs no iteration,
+    # which pays whatever the network cost, so the network runs again on the next step
+    loose = float(np.sqrt(s["rel_res_learned"] * s["rel_res_plain"]))
+    ctx.set_opts(guess_backoff=2)
+    ctx.ensure_workspace(tbs.PREC_MIXED)
+    s1 = ctx.timestep(u, q, un, tbs.PREC_MIXED, loose, 2000, net)
+    assert s1["used_learned_guess"] == 1 and s1["iters"] == 0 and s1["converged"], s1
+    s2 = ctx.timestep(u, q, un, tbs.PREC_MIXED, loose, 2000, net)
+    assert s2["skipped_learned_guess"] == 0 and s2["used_learned_guess"] == 1
 
 
 def test_adam_over_several_steps_matches_oracle():
