@@ -364,6 +364,7 @@ def extras(ctx, tbs, torch, w, u0, stream, net, N, k_all):
     res["apply_degree_sweep"] = degree_sweep(tbs, torch)
     res["transforms"] = transforms(tbs, torch, w, u0)
     res.update(workload_steps(tbs, torch))
+    res.update(graph_cg(tbs, torch))
 
     def time_steps(prec, use_net, k):
         ua, ub = u0.clone(), torch.empty_like(u0)
@@ -571,6 +572,53 @@ def degree_sweep(tbs, torch):
     out["grid"] = list(w.grid)
     out["bc"] = w.bc
     return out
+
+
+def graph_cg(tbs, torch):
+    """The 32^3 periodic FP64 CG solve (rtol 1e-10) eagerly with host convergence polls, and the
+    same number of iterations captured into a HIP graph (poll_every = 0) and replayed: a
+    launch-bound solve where the graph removes the host round trips."""
+    import workloads
+    w = workloads.HEAT_32_PERIODIC
+    g = torch.Generator(device="cpu").manual_seed(w.seed)
+    b = torch.randn(w.grid[::-1], dtype=torch.float64, generator=g).cuda()
+    x = torch.zeros_like(b)
+    eager = tbs.Context(w.grid, w.degree, w.h, w.tau, w.bc)
+    eager.ensure_workspace(tbs.PREC_FP64)
+    reps = 20
+    eager.cg_begin(b, x, w.rtol)
+    _, iters = eager.cg_step(1000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        x.zero_()
+        eager.cg_begin(b, x, w.rtol)
+        eager.cg_step(1000)
+    torch.cuda.synchronize()
+    t_eager = (time.perf_counter() - t0) / reps
+    side = torch.cuda.Stream()
+    cap = tbs.Context(w.grid, w.degree, w.h, w.tau, w.bc, stream=side)
+    cap.set_opts(poll_every=0)
+    cap.ensure_workspace(tbs.PREC_FP64)
+    graph = torch.cuda.CUDAGraph()
+    torch.cuda.synchronize()
+    with torch.cuda.graph(graph, stream=side):
+        x.zero_()  # a fill kernel in the graph: every replay solves from x = 0
+        cap.cg_begin(b, x, w.rtol)
+        cap.cg_step(iters, sync=False)
+    torch.cuda.synchronize()
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        graph.replay()
+    torch.cuda.synchronize()
+    t_graph = (time.perf_counter() - t0) / reps
+    r = {"grid": list(w.grid), "iters": iters, "eager_ms_per_solve": round(t_eager * 1e3, 3),
+         "graph_ms_per_solve": round(t_graph * 1e3, 3)}
+    log("graph cg: %s" % r)
+    del eager, cap, graph
+    return {"cg_graph_32": r}
 
 
 def workload_steps(tbs, torch):

@@ -88,7 +88,12 @@ typedef struct {
                               bf16-stored direction); a sweep asks for max(inner_rtol, rtol / (2 rel)) */
   int inner_max_iter;      /* refinement: inner iteration cap per sweep (default 500) */
   int max_sweeps;          /* refinement: sweep cap (default 12) */
-  int poll_every;          /* CG iterations enqueued between host convergence polls (default 4) */
+  int poll_every;          /* CG iterations enqueued between host convergence polls (default 4).
+                              0 = tbs_cg_step polls never: it enqueues all n_iters iterations (those
+                              after convergence return at once on the device) and the flush, and
+                              with NULL rel_res_out and iters_out nothing in tbs_cg_begin +
+                              tbs_cg_step waits on the host, so the pair can be captured into a HIP
+                              graph and replayed (the other solvers poll every 4 iterations then). */
   int zchunk;              /* z-planes per workgroup of the stencil kernels (0 = automatic); operator
                               outputs do not depend on it (each output sums its terms in the same
                               order); dot products group their terms by workgroup, so it changes

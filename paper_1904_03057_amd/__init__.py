@@ -256,7 +256,12 @@ class Context:
     def cg_begin(self, b, x, rtol):
         _check(_lib.tbs_cg_begin(self._h, _ptr(b), _ptr(x), _dtype_code(x), rtol), "tbs_cg_begin")
 
-    def cg_step(self, n_iters):
+    def cg_step(self, n_iters, sync=True):
+        """n_iters CG iterations; (relative recursive residual, completed iterations), or None
+        without sync (no host read: with poll_every=0 the call is graph-capturable)."""
+        if not sync:
+            _check(_lib.tbs_cg_step(self._h, n_iters, None, None), "tbs_cg_step")
+            return None
         rel, it = ctypes.c_double(), ctypes.c_int()
         _check(_lib.tbs_cg_step(self._h, n_iters, ctypes.byref(rel), ctypes.byref(it)), "tbs_cg_step")
         return rel.value, it.value

@@ -464,7 +464,7 @@ extern "C" int tbs_set_opts(tbs_ctx* c, const tbs_opts* o) {
     c->opts.coarse_guess = 0; c->opts.coarse_rtol = 1e-2; c->opts.guess_backoff = 0; c->opts.guess_test = 0;
   } else {
     if (!(o->inner_rtol > 0 && o->inner_rtol < 1) || o->inner_max_iter < 1 || o->max_sweeps < 1 ||
-        o->poll_every < 1 || o->zchunk < 0 || o->tile_order < 0 || o->tile_order > 1 || o->nt_store < 0 ||
+        o->poll_every < 0 || o->zchunk < 0 || o->tile_order < 0 || o->tile_order > 1 || o->nt_store < 0 ||
         o->nt_store > 1 || o->fused_cg < 0 || o->fused_cg > 1 || o->coarse_guess < 0 || o->coarse_guess > 1 ||
         !(o->coarse_rtol > 0 && o->coarse_rtol < 1) || o->guess_backoff < 0 || o->guess_backoff > 2 ||
         o->guess_test < 0 || o->guess_test > 1)
@@ -811,13 +811,30 @@ static int cgf_async(tbs_ctx* c, const CgArrays& A, int dt, int k) {
 // Runs CG iterations k = k0 .. until done / max_iter, then flushes the pending x update (unless
 // keep_pending: the caller then applies it, e.g. with launch_refine_add, and clears the flag).
 // Returns TBS_OK, TBS_W_NOT_CONVERGED or TBS_E_BREAKDOWN; *nit receives the completed count.
-static int cg_loop(tbs_ctx* c, const CgArrays& A, int dt, int k0, int max_iter, int* nit, bool keep_pending = false) {
+// nopoll: every iteration up to max_iter is enqueued without a host poll (the kernels of a solve
+// that has converged return at once), nothing waits on the host, and *nit receives max_iter.
+static int cg_loop(tbs_ctx* c, const CgArrays& A, int dt, int k0, int max_iter, int* nit, bool keep_pending = false,
+                   bool nopoll = false) {
   int k = k0, rc;
+  if (nopoll) {
+    for (; k < max_iter; ++k) {
+      rc = c->opts.fused_cg ? cgf_async(c, A, dt, k) : cg1_async(c, A, dt, k);
+      if (rc) return rc;
+    }
+    if (!keep_pending) {
+      HIPCHK(launch_flush(A.x, A.p[0], A.p[1], c->N, dt, scal(c, SC_CG), c->st));
+      HIPCHK(launch_finalize(FIN_CLEAR_PENDING, nullptr, nullptr, 0, scal(c, SC_CG), 0.0, c->st));
+      c->cgf_pend = 0;
+    }
+    *nit = k;
+    return TBS_OK;
+  }
   Scalars s;
   rc = read_scal(c, SC_CG, &s);
   if (rc) return rc;
+  const int poll = c->opts.poll_every > 0 ? c->opts.poll_every : 4;
   while (!s.done && k < max_iter) {
-    const int batch = std::min(c->opts.poll_every, max_iter - k);
+    const int batch = std::min(poll, max_iter - k);
     for (int i = 0; i < batch; ++i) {
       rc = c->opts.fused_cg ? cgf_async(c, A, dt, k++) : cg1_async(c, A, dt, k++);
       if (rc) return rc;
@@ -898,7 +915,8 @@ extern "C" int tbs_cg_step(tbs_ctx* c, int n_iters, double* rel_res_out, int* it
     A.r2 = c->ws + L.off[6]; A.q2 = c->ws + L.off[7];
   }
   int nit = 0;
-  rc = cg_loop(c, A, c->cg_dt == TBS_F64 ? 0 : 1, c->cg_enq, c->cg_enq + n_iters, &nit);
+  rc = cg_loop(c, A, c->cg_dt == TBS_F64 ? 0 : 1, c->cg_enq, c->cg_enq + n_iters, &nit, false,
+               c->opts.poll_every == 0);
   c->cg_enq = nit;
   if (rc < 0) return rc;
   if (rel_res_out || iters_out) {
