@@ -101,14 +101,15 @@ typedef struct {
   int tile_order;          /* stencil tile order: 0 x-tiles fastest (default), 1 y-tiles fastest
                               (same effect on results as zchunk) */
   int nt_store;            /* 1: stencil outputs use non-temporal stores (no effect on results) */
-  int fused_cg;            /* FP32 inner CG (TBS_PREC_FP32, MIXED, MIXED_BF16, tbs_cg_step in F32):
+  int fused_cg;            /* CG iteration form (every CG of the library):
                               1 = one kernel per iteration (default): r and p formed while staging,
                               q = A p, and FP64 sums of p.q, r.q, q.q and r.r; alpha = r.r / p.q from
                               the explicit r.r, beta and the stopping test from the one-step
                               prediction r.r - 2 alpha r.q + alpha^2 q.q; 0 = the two-kernel
                               Hestenes-Stiefel iteration (q = A p and p.q, then r -= alpha q and r.r).
-                              Applies to the FP64 CG too (TBS_PREC_FP64, tbs_cg_step in F64,
-                              tbs_transform_interp and the coarse-grid solve). */
+                              FP32 (TBS_PREC_FP32, MIXED, MIXED_BF16, tbs_cg_step in F32) and FP64
+                              (TBS_PREC_FP64, tbs_cg_step in F64, tbs_transform_interp and the
+                              coarse-grid solve) alike. */
   int coarse_guess;        /* 1: tbs_timestep without a network starts from a coarse-grid guess
                               (Sec. 3 leg example: CG started from a reduced-grid solution): the
                               residual of u_prev is restricted to the halved grid, the coarse
@@ -247,11 +248,13 @@ int tbs_stream_copy(tbs_ctx* ctx, const void* src, void* dst, size_t bytes);
  * caller-owned and must stay alive until the last tbs_cg_step.  Asynchronous. */
 int tbs_cg_begin(tbs_ctx* ctx, const void* b, void* x, int dtype, double rtol);
 
-/* Runs up to n_iters more CG iterations (FP64: Hestenes-Stiefel in two kernels; F32: the form
- * tbs_opts.fused_cg selects) and stops once ||r|| <= rtol ||b||, r being the recursive residual
- * (F32 one-kernel form: its one-step prediction), leaving x consistent.  If rel_res_out is not NULL it receives ||r||/||b||
- * and iters_out the total iteration count (both synchronise).  Returns TBS_E_BREAKDOWN on
- * p^T A p <= 0 or non-finite values. */
+/* Runs up to n_iters more CG iterations (the form tbs_opts.fused_cg selects: one kernel per
+ * iteration, or the two-kernel Hestenes-Stiefel iteration) and stops once ||r|| <= rtol ||b||, r
+ * being the recursive residual (one-kernel form: its one-step prediction), leaving x consistent.
+ * It polls the device's convergence flag every tbs_opts.poll_every iterations (which synchronises);
+ * with poll_every 0 it enqueues all n_iters and never waits.  If rel_res_out is not NULL it receives
+ * ||r||/||b|| and iters_out the total iteration count (both synchronise).  Returns
+ * TBS_E_BREAKDOWN on p^T A p <= 0 or non-finite values (with polling). */
 int tbs_cg_step(tbs_ctx* ctx, int n_iters, double* rel_res_out, int* iters_out);
 
 /* ------------------------------------------------------- implicit time step -------------- */
