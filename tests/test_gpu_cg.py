@@ -100,6 +100,29 @@ def test_cg_fp32_one_kernel_other_degrees(n, grid, bc):
     assert abs(rel - hist[-1]) <= 1e-3 * hist[-1], (rel, hist[-1])
 
 
+@pytest.mark.parametrize("n", [1, 3, 5])
+@pytest.mark.parametrize("bc", ["dirichlet", "periodic"])
+@pytest.mark.parametrize("dt,fused", [("f64", 1), ("f64", 0), ("f32", 1), ("f32", 0)])
+def test_cg_on_the_smallest_grid(n, bc, dt, fused):
+    # every axis at the 2n+1 minimum: one partial tile, one z-chunk shorter than its halo; the
+    # iterates of both forms against the oracle's Hestenes-Stiefel CG
+    N = 2 * n + 1
+    grid, tau, k = (N, N, N), 1e-2, 4
+    h = (1.0 / N,) * 3
+    P = tbs.PREC_FP64 if dt == "f64" else tbs.PREC_FP32
+    ctx = _ctx(grid, n, h, tau, bc, P)
+    ctx.set_opts(fused_cg=fused)
+    ctx.ensure_workspace(P)
+    b = rounded(normal_field(grid[::-1], 50 + n), dt)
+    x = dev(np.zeros(grid[::-1]), dt)
+    ctx.cg_begin(dev(b, dt), x, 0.0)
+    rel, it = ctx.cg_step(k)
+    xr, _, hist = solvers.cg(lambda v: op.apply(v, n, h, tau, bc), b, np.zeros_like(b), 0.0, 100, fixed_iters=k)
+    assert it == k
+    tol = 1e-10 if dt == "f64" else 1e-4
+    assert np.linalg.norm(host(x) - xr) <= tol * np.linalg.norm(xr)
+
+
 @pytest.mark.parametrize("split", [(4, 5), (3, 6), (1, 1, 7), (2, 2, 2, 3)])
 def test_cg_fp32_one_kernel_continuation_bitwise(split):
     # r, p and q alternate between two arrays, and x takes its updates two at a time (flushed at the
