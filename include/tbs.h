@@ -139,6 +139,11 @@ typedef struct {
                               products), kept if that A-norm drops, i.e. 2 gamma r0.du - gamma^2
                               du.A du > 0; for the backoff a kept guess that does not halve the plain
                               guess's FP64 residual counts as a rejection. */
+  int fused_rhs;           /* 1 (default): a source-free (q = NULL) refined tbs_timestep that starts
+                              from the plain guess (no network run, no coarse guess) on a periodic or
+                              Dirichlet grid forms b = M u^k and the first residual b - A u^k in one
+                              pass over u^k (b bit for bit the rhs kernel's); 0: rhs kernel, then
+                              residual kernel. */
 } tbs_opts;
 
 /* ---------------------------------------------------------------- context ---------------- */
@@ -355,8 +360,8 @@ int tbs_net_get_grad(const tbs_net* net, float* host, size_t n);
  * 6 cg-fused f32, 7 cg-fused f32 with bf16 p, 8 residual f64, 9 cg-update f64, 10 cg-update f32,
  * 11 one-kernel CG iteration f32, 12 one-kernel CG iteration f32 with bf16 p, 13 variable-coefficient
  * apply f64, 14 variable-coefficient apply f32 (bytes: u, d, m read and y written once), 15 one-kernel
- * CG iteration f64. */
-#define TBS_PROF_KINDS 16
+ * CG iteration f64, 16 fused rhs and residual f64 (u read, b and the FP32 r written). */
+#define TBS_PROF_KINDS 17
 int tbs_prof_enable(tbs_ctx* ctx, int on);   /* resets the counters */
 int tbs_prof_read(tbs_ctx* ctx, int kind, double* total_ms, double* total_bytes, int64_t* launches);
 

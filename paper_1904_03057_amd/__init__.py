@@ -39,7 +39,7 @@ EXPORTS = [
 ]
 PROF_KINDS = ["apply_f64", "apply_f32", "apply_bf16_f32", "rhs_f64", "rhs_f32", "cg_fused_f64", "cg_fused_f32",
               "cg_fused_f32_bf16p", "residual_f64", "cg_update_f64", "cg_update_f32", "cg_iter_f32",
-              "cg_iter_f32_bf16p", "varcoef_f64", "varcoef_f32", "cg_iter_f64"]
+              "cg_iter_f32_bf16p", "varcoef_f64", "varcoef_f32", "cg_iter_f64", "rhs_resid_f64"]
 
 
 class Stats(ctypes.Structure):
@@ -60,7 +60,7 @@ class Opts(ctypes.Structure):
                 ("max_sweeps", ctypes.c_int), ("poll_every", ctypes.c_int), ("zchunk", ctypes.c_int),
                 ("tile_order", ctypes.c_int), ("nt_store", ctypes.c_int), ("fused_cg", ctypes.c_int),
                 ("coarse_guess", ctypes.c_int), ("coarse_rtol", ctypes.c_double), ("guess_backoff", ctypes.c_int),
-                ("guess_test", ctypes.c_int)]
+                ("guess_test", ctypes.c_int), ("fused_rhs", ctypes.c_int)]
 
 
 _vp, _i64p, _dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)
@@ -200,9 +200,9 @@ class Context:
 
     def set_opts(self, inner_rtol=1e-6, inner_max_iter=500, max_sweeps=12, poll_every=4, zchunk=0,
                  tile_order=0, nt_store=0, fused_cg=1, coarse_guess=0, coarse_rtol=1e-2, guess_backoff=0,
-                 guess_test=0):
+                 guess_test=0, fused_rhs=1):
         o = Opts(inner_rtol, inner_max_iter, max_sweeps, poll_every, zchunk, tile_order, nt_store, fused_cg,
-                 coarse_guess, coarse_rtol, guess_backoff, guess_test)
+                 coarse_guess, coarse_rtol, guess_backoff, guess_test, fused_rhs)
         _check(_lib.tbs_set_opts(self._h, ctypes.byref(o)), "tbs_set_opts")
         # options can change the workspace layout (partial-sum count, coarse-guess region): the
         # library drops its binding then; rebind the buffer if it still holds the minimum

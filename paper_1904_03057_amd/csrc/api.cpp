@@ -304,6 +304,7 @@ extern "C" int tbs_setup(tbs_ctx** out, const int64_t grid[3], int degree, const
   c->opts.fused_cg = 1;
   c->opts.coarse_guess = 0;
   c->opts.coarse_rtol = 1e-2;
+  c->opts.fused_rhs = 1;
   *out = c;
   return TBS_OK;
 }
@@ -462,12 +463,13 @@ extern "C" int tbs_set_opts(tbs_ctx* c, const tbs_opts* o) {
     c->opts.inner_rtol = 1e-6; c->opts.inner_max_iter = 500; c->opts.max_sweeps = 12; c->opts.poll_every = 4;
     c->opts.zchunk = 0; c->opts.tile_order = 0; c->opts.nt_store = 0; c->opts.fused_cg = 1;
     c->opts.coarse_guess = 0; c->opts.coarse_rtol = 1e-2; c->opts.guess_backoff = 0; c->opts.guess_test = 0;
+    c->opts.fused_rhs = 1;
   } else {
     if (!(o->inner_rtol > 0 && o->inner_rtol < 1) || o->inner_max_iter < 1 || o->max_sweeps < 1 ||
         o->poll_every < 0 || o->zchunk < 0 || o->tile_order < 0 || o->tile_order > 1 || o->nt_store < 0 ||
         o->nt_store > 1 || o->fused_cg < 0 || o->fused_cg > 1 || o->coarse_guess < 0 || o->coarse_guess > 1 ||
         !(o->coarse_rtol > 0 && o->coarse_rtol < 1) || o->guess_backoff < 0 || o->guess_backoff > 2 ||
-        o->guess_test < 0 || o->guess_test > 1)
+        o->guess_test < 0 || o->guess_test > 1 || o->fused_rhs < 0 || o->fused_rhs > 1)
       return set_err(TBS_E_INVAL, "bad options");
     if (o->coarse_guess) {
       if (c->transform_degree) return set_err(TBS_E_INVAL, "coarse guess on a transform context");
@@ -601,6 +603,20 @@ extern "C" int tbs_apply_varcoef(tbs_ctx* c, const void* u, const void* d, const
   const int ps = prof_begin(c, dt == TBS_F64 ? 13 : 14, -1, (double)c->N * 4 * esz);
   HIPCHK(launch_varcoef(a, n, c->bc, dt == TBS_F64 ? 0 : 1, c->st));
   prof_end(c, ps);
+  return TBS_OK;
+}
+
+// b = M u (FP64) and r = b - A u (FP32) in one pass (source-free step, no Robin), norms to scal slot
+static int rhs_resid_async(tbs_ctx* c, const double* u, double* b, void* r, int slot) {
+  StencilArgs a = base_args(c);
+  a.in0 = u;
+  a.out1 = b;
+  a.out0 = r;
+  const int ps = prof_begin(c, 16, -1, (double)c->N * (8 + 8 + 4));
+  HIPCHK(launch_rhs_resid(a, c->n, c->bc, c->st));
+  prof_end(c, ps);
+  HIPCHK(launch_finalize(FIN_NORMS, part0(c), part1(c), stencil_blocks(a, M_RHSRES, 8, c->n, c->bc), scal(c, slot), 0.0,
+                         c->st));
   return TBS_OK;
 }
 
@@ -1003,19 +1019,36 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
   st.rel_res_learned = NAN;
   st.rel_res_coarse = NAN;
 
-  // right-hand side, FP64 except for the raw FP32 path (which builds its FP64 b after the solve)
-  double* b64 = (prec == TBS_PREC_FP32) ? nullptr : (double*)(c->ws + L.off[0]);
-  if (prec != TBS_PREC_FP32) {
-    rc = tbs_rhs(c, u_prev, q, b64, TBS_F64);
-    if (rc) return rc;
-  }
-
   // the network is run unless the backoff policy is waiting out an earlier rejection
   tbs_net* g = (prec != TBS_PREC_FP32) ? net : nullptr;
   if (g && c->opts.guess_backoff && c->guess_wait > 0) {
     --c->guess_wait;
     g = nullptr;
     st.skipped_learned_guess = 1;
+  }
+
+  // refined path: the plain guess's residual (FP32 copy, norms and partial sums) is the first
+  // refinement sweep's residual whenever the plain guess is kept, so it is computed last and reused
+  bool have_res0 = false;
+  Scalars res0{};
+  // right-hand side, FP64 except for the raw FP32 path (which builds its FP64 b after the solve).
+  // A source-free refined step that starts from the plain guess forms b = M u and the first
+  // sweep's residual b - A u in one pass over u (the same b, bit for bit, as the rhs kernel's)
+  double* b64 = (prec == TBS_PREC_FP32) ? nullptr : (double*)(c->ws + L.off[0]);
+  if (prec != TBS_PREC_FP32) {
+    const bool refined_path = (prec == TBS_PREC_MIXED || prec == TBS_PREC_MIXED_BF16);
+    const bool fused_rhs = refined_path && !q && !g && c->bc != TBS_BC_ROBIN && c->opts.fused_rhs &&
+                           !(c->coarse && c->opts.coarse_guess);
+    if (fused_rhs) {
+      rc = rhs_resid_async(c, u_prev, b64, c->ws + L.off[1], SC_AUX);
+      if (rc) return rc;
+      rc = read_scal(c, SC_AUX, &res0);
+      if (rc) return rc;
+      have_res0 = true;
+    } else {
+      rc = tbs_rhs(c, u_prev, q, b64, TBS_F64);
+      if (rc) return rc;
+    }
   }
   // cost-aware backoff: events around the network and its test, and around the rest of the step
   const bool costed = g && c->opts.guess_backoff == 2;
@@ -1042,10 +1075,6 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     have_x = true;
     return copy_async(c, u_next, u_prev, N * 8);
   };
-  // refined path: the plain guess's residual (FP32 copy, norms and partial sums) is the first
-  // refinement sweep's residual whenever the plain guess is kept, so it is computed last and reused
-  bool have_res0 = false;
-  Scalars res0{};
   if (g) {
     const float* du = nullptr;
     const int64_t grid[3] = {c->nx, c->ny, c->nz};

@@ -34,8 +34,9 @@ struct Scalars {
 static_assert(sizeof(Scalars) <= 256, "a Scalars slot of the workspace is 256 bytes");
 
 // CG1: one half of a Hestenes-Stiefel iteration (p, x update, q = A p, p.q); CGF: a whole iteration
-// in one kernel (r update, p, x update, q = A p and the dot products p.q, r.q, q.q, r.r).
-enum Mode { M_APPLY = 0, M_RHS = 1, M_CG1 = 2, M_RESID = 3, M_CGF = 4 };
+// in one kernel (r update, p, x update, q = A p and the dot products p.q, r.q, q.q, r.r); RHSRES:
+// the right-hand side b = M u of a source-free step and its residual r = b - A u in one pass.
+enum Mode { M_APPLY = 0, M_RHS = 1, M_CG1 = 2, M_RESID = 3, M_CGF = 4, M_RHSRES = 5 };
 enum Bc { BC_PERIODIC = 0, BC_DIRICHLET = 1, BC_ROBIN = 2 };
 
 // Robin / penalty boundary on a box (BC_ROBIN): every 1-D factor of the operator is the truncated
@@ -59,10 +60,10 @@ struct StencilArgs {
   const void* in1;             // RHS: q (nullable)  CG1, CGF: p_old
   const void* in2;             // CGF: q_old
   void* out0;                  // APPLY: y  RHS: b  CG1, CGF: q  RESID: r (nullable)
-  void* out1;                  // CG1, CGF: p_new
+  void* out1;                  // CG1, CGF: p_new  RHSRES: b (f64)
   void* out2;                  // CGF: r_new
   void* io0;                   // CG1, CGF: x (lazy update, nullable)
-  const double* bvec;          // RESID: b
+  const double* bvec;          // RESID: b (RHSRES: formed in the kernel)
   double* part0;               // per-block partial sums (CG1, CGF: p.q, RESID: r.r)
   double* part1;               // RESID: b.b  CGF: r.q
   double* part2;               // CGF: q.q

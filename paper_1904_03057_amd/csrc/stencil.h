@@ -69,19 +69,23 @@ constexpr int stencil_tile_y(int mode, int compute_bytes, int n, int bc) {
   return compute_bytes == 4
              ? ((mode == M_APPLY) ? 32
                                   : (mode == M_CG1 ? STENCIL_CG_TY : (mode == M_CGF ? cgf_tile_y(n, bc, 4) : 16)))
-             : (mode == M_RESID ? STENCIL_RESID_TY : (mode == M_CGF ? cgf_tile_y(n, bc, 8) : 16));
+             : ((mode == M_RESID || mode == M_RHSRES) ? STENCIL_RESID_TY : (mode == M_CGF ? cgf_tile_y(n, bc, 8) : 16));
 }
 // Row waves per workgroup: four for the FP32 kernels, except the one-kernel CG iteration, whose
 // waves keep four rows each (two in FP64); eight for the other FP64 kernels.
 constexpr int stencil_tile_wy(int mode, int compute_bytes, int n, int bc) {
   return mode == M_CGF ? stencil_tile_y(mode, compute_bytes, n, bc) / cgf_rows_per_wave(compute_bytes)
-                       : (mode == M_RESID ? STENCIL_RESID_WY : (compute_bytes == 8 ? STENCIL_F64_WY : 4));
+                       : ((mode == M_RESID || mode == M_RHSRES) ? STENCIL_RESID_WY
+                                                                   : (compute_bytes == 8 ? STENCIL_F64_WY : 4));
 }
 // One stencil launch of degree N for a (mode, input, compute, output) type combination and
 // boundary condition BC; defined in stencil_kernel.h and instantiated per degree and boundary
 // condition by stencil_inst.hip.
 template <int N, int MODE, typename Tin, typename Tc, typename Tout, int BC>
 hipError_t launch_bcx(const StencilArgs& a, bool vec, hipStream_t st);
+
+template <int N, int BC>
+hipError_t launch_rhsres_bc(const StencilArgs& a, bool vec, hipStream_t st);
 
 template <int N, int MODE, typename Tin, typename Tc, typename Tout>
 inline hipError_t launch_bc(const StencilArgs& a, int bc, bool vec, hipStream_t st) {
@@ -100,6 +104,9 @@ hipError_t launch_cg1(const StencilArgs& a, int n, int bc, int dt, hipStream_t s
 // CGF (one-kernel CG iteration): dt = 1 (all f32), 2 (f32 with p stored as bf16)
 hipError_t launch_cgf(const StencilArgs& a, int n, int bc, int dt, hipStream_t st);
 hipError_t launch_resid(const StencilArgs& a, int n, int bc, int r_dt, hipStream_t st);
+// RHSRES: u (f64, in0) -> b = M u (f64, out1) and r = (b - A u) rscale (f32, out0), with the partial
+// sums of r.r and (b rscale).(b rscale); periodic and Dirichlet only (hipErrorInvalidValue on Robin)
+hipError_t launch_rhs_resid(const StencilArgs& a, int n, int bc, hipStream_t st);
 
 // vector.hip
 constexpr int kVecBlocks = 2048;   // grid of the elementwise kernels (= partial sums they write)

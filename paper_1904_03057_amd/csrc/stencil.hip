@@ -64,4 +64,18 @@ hipError_t launch_resid(const StencilArgs& a, int n, int bc, int r_dt, hipStream
   return hipErrorInvalidValue;
 }
 
+hipError_t launch_rhs_resid(const StencilArgs& a, int n, int bc, hipStream_t st) {
+  const bool vec = (a.nx % 2) == 0;  // 16-byte staging of the FP64 input
+  if (bc == BC_ROBIN) return hipErrorInvalidValue;
+  const bool per = bc == BC_PERIODIC;
+  switch (n) {
+    case 1: return per ? launch_rhsres_bc<1, BC_PERIODIC>(a, vec, st) : launch_rhsres_bc<1, BC_DIRICHLET>(a, vec, st);
+    case 2: return per ? launch_rhsres_bc<2, BC_PERIODIC>(a, vec, st) : launch_rhsres_bc<2, BC_DIRICHLET>(a, vec, st);
+    case 3: return per ? launch_rhsres_bc<3, BC_PERIODIC>(a, vec, st) : launch_rhsres_bc<3, BC_DIRICHLET>(a, vec, st);
+    case 4: return per ? launch_rhsres_bc<4, BC_PERIODIC>(a, vec, st) : launch_rhsres_bc<4, BC_DIRICHLET>(a, vec, st);
+    case 5: return per ? launch_rhsres_bc<5, BC_PERIODIC>(a, vec, st) : launch_rhsres_bc<5, BC_DIRICHLET>(a, vec, st);
+  }
+  return hipErrorInvalidValue;
+}
+
 }  // namespace tbs

@@ -58,6 +58,9 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
   constexpr int NV = NVC + NVH;
   constexpr int RPW = TY / WY;                     // output rows per wave
   constexpr bool CG = (MODE == M_CG1 || MODE == M_CGF);
+  constexpr bool RR = (MODE == M_RHSRES);  // b = M u and r = b - A u in one pass (no Robin corners)
+  constexpr bool RES = (MODE == M_RESID || RR);
+  static_assert(!(RR && BC == BC_ROBIN), "the fused rhs and residual has no Robin corner terms");
   constexpr bool FUSED = (MODE == M_CGF);
   constexpr int QD = CG ? N + 1 : 1;  // depth of the centre-value rings (CG1, CGF)
   static_assert(TY % WY == 0, "TY must be a multiple of the row waves");
@@ -195,7 +198,7 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
   // prefetch registers: primary input vector (u / u_prev / p_old / x), secondary (q / r), x (CG1)
   // two prefetch slots: plane k is staged from slot (k - kbeg) & 1 while plane k+1 is in flight
   // prefetch distance (planes); 1 keeps the registers of the residual (and CG1) low
-  constexpr int PF = MODE == M_RESID ? 1 : (CG ? STENCIL_CG_PF : 2);
+  constexpr int PF = RES ? 1 : (CG ? STENCIL_CG_PF : 2);
   Raw pa[PF][NV];
   RawC pb[PF][NV];
   RawC px[PF][NVC];
@@ -227,7 +230,7 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
       }
       if (pvalid && ((valid >> v) & 1u)) {
         const int64_t gi = base + off[v];
-        if (MODE == M_APPLY || MODE == M_RESID) {
+        if (MODE == M_APPLY || RES) {
           pa[sl][v] = *(const Raw*)((const Tin*)a.in0 + gi);
         } else if (MODE == M_RHS) {
           pa[sl][v] = *(const Raw*)((const Tin*)a.in0 + gi);
@@ -256,7 +259,7 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
     for (int v = 0; v < NV; ++v) {
       if (soff[v] >= 0) {
         Tc* dst = stage + soff[v];
-        if (MODE == M_APPLY || MODE == M_RESID) {
+        if (MODE == M_APPLY || RES) {
 #pragma unroll
           for (int e = 0; e < VE; ++e) dst[e] = to_c<Tin, Tc>(pa[sl][v].x[e]);
         } else if (MODE == M_RHS) {
@@ -303,10 +306,14 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
   };
 
   Tc acc[T][RPW];
+  Tc accb[RR ? T : 1][RR ? RPW : 1];  // RHSRES: M u (= Mz P), the right-hand side
 #pragma unroll
   for (int s = 0; s < T; ++s)
 #pragma unroll
-    for (int i = 0; i < RPW; ++i) acc[s][i] = (Tc)0;
+    for (int i = 0; i < RPW; ++i) {
+      acc[s][i] = (Tc)0;
+      if (RR) accb[RR ? s : 0][RR ? i : 0] = (Tc)0;
+    }
   // BC_ROBIN: z-corner contributions to the output planes j-th from an end, j < ZM, kept in LDS
   // (each thread only touches its own column and rows)
   constexpr int ZM = BC == BC_ROBIN ? 2 * (N / 2) + 1 : 1;
@@ -432,6 +439,7 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
             } else {
               acc[s][i] = fmad(m[ad], Rr, acc[s][i]);
               acc[s][i] = fmad(azs[ad], P, acc[s][i]);
+              if (RR) accb[RR ? s : 0][RR ? i : 0] = fmad(m[ad], P, accb[RR ? s : 0][RR ? i : 0]);
             }
           }
           if constexpr (BC == BC_ROBIN) {
@@ -495,7 +503,14 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
               } else {
                 // rscale (a power of two, 1 unless the refinement keeps r inside FP32 range) scales
                 // the stored residual and both sums alike: their ratio is unchanged
-                const double b = a.bvec[gi] * a.rscale;
+                double b0;
+                if constexpr (RR) {
+                  b0 = (double)accb[RR ? so : 0][RR ? i : 0];
+                  ((double*)a.out1)[gi] = b0;  // the step's right-hand side, as the rhs kernel forms it
+                } else {
+                  b0 = a.bvec[gi];
+                }
+                const double b = b0 * a.rscale;
                 const double r = b - (double)val * a.rscale;
                 if (a.out0) Io<Tout>::template st<double>(a.out0, gi, r);
                 part0 = fma(r, r, part0);
@@ -505,13 +520,16 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
           }
         }
 #pragma unroll
-        for (int i = 0; i < RPW; ++i) acc[so][i] = (Tc)0;
+        for (int i = 0; i < RPW; ++i) {
+          acc[so][i] = (Tc)0;
+          if (RR) accb[RR ? so : 0][RR ? i : 0] = (Tc)0;
+        }
       }
       }
     }
   }
 
-  if (CG || MODE == M_RESID) {
+  if (CG || RES) {
     part0 = wave_sum(part0);
     part1 = wave_sum(part1);
     if (FUSED) {
@@ -525,7 +543,7 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
 #pragma unroll
       for (int q = 0; q < WY * WX; ++q) { s0 += red[0][q]; s1 += red[1][q]; s2 += red[2][q]; s3 += red[3][q]; }
       a.part0[blockIdx.x] = s0;
-      if (MODE == M_RESID || FUSED) a.part1[blockIdx.x] = s1;
+      if (RES || FUSED) a.part1[blockIdx.x] = s1;
       if (FUSED) { a.part2[blockIdx.x] = s2; a.part3[blockIdx.x] = s3; }
     }
   }
@@ -567,6 +585,17 @@ hipError_t launch_bcx(const StencilArgs& a0, bool vec, hipStream_t st) {
   return hipGetLastError();
 }
 
+// The fused rhs and residual for degree N and boundary BC (no Robin instance: the caller falls back
+// to the rhs and residual kernels there).
+template <int N, int BC>
+hipError_t launch_rhsres_bc(const StencilArgs& a, bool vec, hipStream_t st) {
+  if constexpr (BC == BC_ROBIN) {
+    return hipErrorInvalidValue;
+  } else {
+    return launch_bcx<N, M_RHSRES, double, double, float, BC>(a, vec, st);
+  }
+}
+
 }  // namespace tbs
 
 // Every (mode, dtype) combination the dispatch in stencil.hip uses, for degree N and boundary BC.
@@ -587,4 +616,5 @@ hipError_t launch_bcx(const StencilArgs& a0, bool vec, hipStream_t st) {
   template hipError_t launch_bcx<N, M_CGF, uint16_t, float, float, BC>(const StencilArgs&, bool, hipStream_t);     \
   template hipError_t launch_bcx<N, M_RESID, double, double, double, BC>(const StencilArgs&, bool, hipStream_t);   \
   template hipError_t launch_bcx<N, M_RESID, double, double, float, BC>(const StencilArgs&, bool, hipStream_t);    \
+  template hipError_t launch_rhsres_bc<N, BC>(const StencilArgs&, bool, hipStream_t);                               \
   }

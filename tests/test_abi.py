@@ -106,7 +106,7 @@ def test_set_opts_validation_without_gpu():
     assert lib.tbs_set_opts(p, ctypes.byref(good)) == tbs.OK
     assert lib.tbs_set_opts(p, None) == tbs.OK
     for field, bad in (("guess_backoff", 3), ("guess_backoff", -1), ("fused_cg", 2), ("inner_rtol", 0.0),
-                       ("coarse_rtol", 1.0), ("poll_every", -1), ("guess_test", 2), ("guess_test", -1)):
+                       ("coarse_rtol", 1.0), ("poll_every", -1), ("guess_test", 2), ("guess_test", -1), ("fused_rhs", 2)):
         o = tbs.Opts(1e-6, 500, 12, 4, 0, 0, 0, 1, 0, 1e-2, 0)
         setattr(o, field, bad)
         assert lib.tbs_set_opts(p, ctypes.byref(o)) == tbs.E_INVAL, field

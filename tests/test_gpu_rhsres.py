@@ -1,0 +1,52 @@
+"""The fused right-hand side and first residual of a source-free refined step (one pass over u^k
+forming b = M u^k and b - A u^k) against the separate rhs and residual kernels: the steps agree bit
+for bit, and their answers pass the oracle's residual test."""
+import numpy as np
+import pytest
+
+from oracle import operator as op, solvers
+from tests.gpu_util import dev, host
+from workloads import normal_field
+
+pytestmark = pytest.mark.gpu
+tbs = pytest.importorskip("paper_1904_03057_amd")
+
+
+@pytest.mark.parametrize("n,grid,bc", [(1, (23, 17, 9), "dirichlet"), (3, (70, 22, 20), "dirichlet"),
+                                       (3, (64, 24, 18), "periodic"), (5, (45, 19, 21), "periodic"),
+                                       (2, (37, 50, 13), "dirichlet")])
+@pytest.mark.parametrize("prec", ["MIXED", "MIXED_BF16"])
+def test_fused_rhs_and_residual_step_equals_separate_kernels(n, grid, bc, prec):
+    h = tuple(1.0 / N for N in grid)
+    tau, rtol = 2e-3, 1e-9
+    P = getattr(tbs, "PREC_" + prec)
+    u = normal_field(grid[::-1], 60 + n)
+    outs, stats = [], []
+    for fused in (1, 0):
+        ctx = tbs.Context(grid, n, h, tau, bc)
+        ctx.set_opts(fused_rhs=fused)
+        ctx.ensure_workspace(P)
+        un = dev(np.zeros(grid[::-1]))
+        st = ctx.timestep(dev(u), None, un, P, rtol, 2000)
+        assert st["converged"], st
+        outs.append(host(un))
+        stats.append(st)
+    assert np.array_equal(outs[0], outs[1])
+    assert stats[0]["iters"] == stats[1]["iters"] and stats[0]["sweeps"] == stats[1]["sweeps"]
+    assert stats[0]["rel_res0"] == stats[1]["rel_res0"]
+    # the oracle's FP64 residual of the answer
+    b = op.rhs(u, None, n, tau, bc)
+    assert solvers.rel_residual(lambda v: op.apply(v, n, h, tau, bc), b, outs[0]) <= rtol * 1.01
+
+
+def test_fused_rhs_is_not_taken_with_a_source():
+    # with q the step takes the rhs and residual kernels; q = 0 gives the same answer as q = None
+    grid, n, bc = (40, 24, 18), 3, "dirichlet"
+    h = tuple(1.0 / N for N in grid)
+    u = normal_field(grid[::-1], 7)
+    ctx = tbs.Context(grid, n, h, 1e-3, bc)
+    ctx.ensure_workspace(tbs.PREC_MIXED)
+    a, b = dev(np.zeros(grid[::-1])), dev(np.zeros(grid[::-1]))
+    s1 = ctx.timestep(dev(u), None, a, tbs.PREC_MIXED, 1e-9, 2000)
+    s2 = ctx.timestep(dev(u), dev(np.zeros(grid[::-1])), b, tbs.PREC_MIXED, 1e-9, 2000)
+    assert np.array_equal(host(a), host(b)) and s1["iters"] == s2["iters"]
