@@ -80,7 +80,8 @@ typedef struct {
                               ln(rel_res_learned / rel_res_plain) / ln(rho), rho the solve's mean
                               residual reduction per iteration; 0 otherwise */
   double learned_cost_iters;   /* guess_backoff 2, network run: the time of the network and its test
-                              in units of this step's time per CG iteration; 0 otherwise */
+                              in units of this step's time per CG iteration (its CG loops' time over
+                              their iterations); 0 otherwise */
 } tbs_stats;
 
 typedef struct {

@@ -164,7 +164,7 @@ struct tbs_ctx {
   int64_t cgrid[3];
   // learned-guess backoff (opts.guess_backoff): consecutive rejections, steps left to skip
   int guess_rejects, guess_wait;
-  hipEvent_t cost_ev[4];  // guess_backoff 2: network + test start / end, solve start / end
+  hipEvent_t cost_ev[4];  // guess_backoff 2: network + test start / end; step end or CG loop start / end
   bool cost_ev_made;
   int cgf_pend;  // host copy of the pending x-update count of the one-kernel CG (for its byte count)
   // CG session state (tbs_cg_begin / tbs_cg_step)
@@ -1001,6 +1001,16 @@ static int fp64_relres(tbs_ctx* c, const double* x, const double* b, double* rel
   return TBS_OK;
 }
 
+// guess_backoff 2: adds the time since cost_ev[2] (recorded before a CG loop) to *ms
+static int cost_lap(tbs_ctx* c, double* ms) {
+  HIPCHK(hipEventRecord(c->cost_ev[3], c->st));
+  HIPCHK(hipEventSynchronize(c->cost_ev[3]));
+  float t = 0.f;
+  HIPCHK(hipEventElapsedTime(&t, c->cost_ev[2], c->cost_ev[3]));
+  *ms += t;
+  return TBS_OK;
+}
+
 extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, double* u_next, int prec, double rtol,
                             int max_iter, tbs_net* net, tbs_stats* stats) {
   if (!c) return set_err(TBS_E_INVAL, "null context");
@@ -1064,6 +1074,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     }
     HIPCHK(hipEventRecord(c->cost_ev[0], c->st));
   }
+  double t_cg = 0.0;  // guess_backoff 2: time of this step's CG loops (ms)
 
   // initial guess: plain u^k, or the network guess if its FP64 residual is smaller.  The current
   // iterate is u_next once have_x is set, else u_prev itself: u_next is only written when a guess
@@ -1222,7 +1233,9 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     if (!g && !st.used_coarse_guess && std::isnan(st.rel_res_coarse)) st.rel_res_plain = st.rel_res0;
     if (st.used_learned_guess) st.rel_res_learned = st.rel_res0;
     int nit = 0;
+    if (costed) HIPCHK(hipEventRecord(c->cost_ev[2], c->st));
     result = cg_loop(c, A, 0, 0, max_iter, &nit);
+    if (costed && (rc = cost_lap(c, &t_cg))) return rc;
     st.iters = nit;
     if (result < 0 && result != TBS_E_BREAKDOWN) return result;
     rc = fp64_relres(c, u_next, b64, &st.rel_res_fp64);
@@ -1262,16 +1275,31 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     float* d32 = (float*)(c->ws + L.off[2]);
     CgArrays A{d32, r32, {c->ws + L.off[3], c->ws + L.off[4]}, c->ws + L.off[5], c->ws + L.off[6], c->ws + L.off[7]};
     int total = 0, sweeps = 0;
+    // a check expected to pass (the last sweep met its inner tolerance eta and rel eta <= rtol, rel
+    // the residual it started from) first forms only the norms; the FP32 residual is stored only if
+    // it fails after all
+    bool expect_pass = false;
     for (;;) {
       Scalars s;
       double rscale = 1.0;  // the stored FP32 residual is r * rscale; the correction is scaled back
       if (sweeps == 0 && have_res0) {
         s = res0;  // r32 and the residual partial sums of u_next = u_prev are already in place
       } else {
-        rc = resid_async(c, have_x ? u_next : u_prev, b64, r32, TBS_F32, SC_AUX, FIN_NORMS, 0.0);
-        if (rc) return rc;
-        rc = read_scal(c, SC_AUX, &s);
-        if (rc) return rc;
+        bool need_r = true;
+        if (expect_pass && have_x) {
+          rc = resid_async(c, u_next, b64, nullptr, TBS_F32, SC_AUX, FIN_NORMS, 0.0);
+          if (rc) return rc;
+          rc = read_scal(c, SC_AUX, &s);
+          if (rc) return rc;
+          const double relc = s.out2 > 0 ? std::sqrt(s.out / s.out2) : std::sqrt(s.out);
+          need_r = !(relc <= rtol || s.out2 == 0.0);
+        }
+        if (need_r) {
+          rc = resid_async(c, have_x ? u_next : u_prev, b64, r32, TBS_F32, SC_AUX, FIN_NORMS, 0.0);
+          if (rc) return rc;
+          rc = read_scal(c, SC_AUX, &s);
+          if (rc) return rc;
+        }
       }
       {
         // the inner FP32 solve sees r / s (the refinement's scaling, a power of two near the RMS of
@@ -1298,6 +1326,7 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
       // inner solve A d = r32 from d = 0 to relative tolerance eta (no tighter than needed)
       // a bf16-stored direction limits the attainable inner accuracy: never ask it for less than 1e-4
       const double eta = std::max(std::max(c->opts.inner_rtol, dt == 2 ? 1e-4 : 0.0), 0.5 * rtol / rel);
+      expect_pass = (rel * eta <= rtol);
       HIPCHK(launch_fill(d32, 1, c->N, c->st));
       HIPCHK(launch_finalize(FIN_INIT, part0(c), part0(c), stencil_blocks(base_args(c), M_RESID, 8, c->n, c->bc), scal(c, SC_CG),
                              eta, c->st));
@@ -1305,8 +1334,11 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
       const int cap = std::min(c->opts.inner_max_iter, std::max(1, max_iter - total));
       // the inner solve's last x update is left pending and applied by the refinement update:
       // u_next = (u_next or u_prev) + (d + alpha p) in one pass over the arrays
+      if (costed) HIPCHK(hipEventRecord(c->cost_ev[2], c->st));
       int irc = cg_loop(c, A, dt, 0, cap, &nit, true);
+      if (costed && (rc = cost_lap(c, &t_cg))) return rc;
       total += nit;
+      expect_pass = expect_pass && irc == TBS_OK;
       if (irc == TBS_E_BREAKDOWN && nit == 0) { result = irc; break; }
       if (irc < 0 && irc != TBS_E_BREAKDOWN) return irc;
       HIPCHK(launch_refine_add(u_next, have_x ? u_next : u_prev, d32, A.p[0], A.p[1], c->N, dt, scal(c, SC_CG),
@@ -1328,13 +1360,13 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
     int wait = 0;
     if (costed) {
       // cost-aware: the kept guess saved ln(learned / plain) / ln(rho) iterations, rho the solve's mean
-      // residual reduction per iteration; it paid if they took longer than the network and its test
-      HIPCHK(hipEventRecord(c->cost_ev[2], c->st));
-      HIPCHK(hipEventSynchronize(c->cost_ev[2]));
-      float t_guess = 0.f, t_solve = 0.f;
+      // residual reduction per iteration; it paid if they took longer than the network and its test.
+      // An iteration's time is the CG loops' time over their iterations (the step's fixed work, its
+      // right-hand side and residual checks, is not saved by a better guess)
+      HIPCHK(hipEventSynchronize(c->cost_ev[1]));
+      float t_guess = 0.f;
       HIPCHK(hipEventElapsedTime(&t_guess, c->cost_ev[0], c->cost_ev[1]));
-      HIPCHK(hipEventElapsedTime(&t_solve, c->cost_ev[1], c->cost_ev[2]));
-      const double t_iter = st.iters > 0 ? (double)t_solve / st.iters : 0.0;
+      const double t_iter = st.iters > 0 ? t_cg / st.iters : 0.0;
       st.learned_cost_iters = t_iter > 0.0 ? t_guess / t_iter : 0.0;
       double saved = 0.0;
       if (st.used_learned_guess && st.iters > 0 && st.rel_res0 > 0.0 && st.rel_res_fp64 > 0.0 &&

@@ -1,6 +1,7 @@
 """The fused right-hand side and first residual of a source-free refined step (one pass over u^k
 forming b = M u^k and b - A u^k) against the separate rhs and residual kernels: the steps agree bit
-for bit, and their answers pass the oracle's residual test."""
+for bit, and their answers pass the oracle's residual test.  Also the sweeps' convergence checks
+(norms only when a check is expected to pass) at tolerances down to 1e-12."""
 import numpy as np
 import pytest
 
@@ -50,3 +51,24 @@ def test_fused_rhs_is_not_taken_with_a_source():
     s1 = ctx.timestep(dev(u), None, a, tbs.PREC_MIXED, 1e-9, 2000)
     s2 = ctx.timestep(dev(u), dev(np.zeros(grid[::-1])), b, tbs.PREC_MIXED, 1e-9, 2000)
     assert np.array_equal(host(a), host(b)) and s1["iters"] == s2["iters"]
+
+
+@pytest.mark.parametrize("rtol", [1e-8, 1e-10, 1e-12])
+@pytest.mark.parametrize("n,grid,bc", [(3, (70, 22, 20), "dirichlet"), (2, (64, 24, 18), "periodic")])
+def test_refined_steps_convergence_checks(n, grid, bc, rtol):
+    # each sweep's check of the refined step: a check expected to pass forms only the norms and
+    # stores the FP32 residual only if it fails; whichever way it goes, every answer meets rtol in
+    # the oracle's FP64 residual
+    print("check", n, grid, bc, rtol, flush=True)
+    h = tuple(1.0 / N for N in grid)
+    tau = 2e-3
+    ctx = tbs.Context(grid, n, h, tau, bc)
+    ctx.ensure_workspace(tbs.PREC_MIXED)
+    u = normal_field(grid[::-1], 90 + n)
+    ua, ub = dev(u), dev(np.zeros(grid[::-1]))
+    for _ in range(3):
+        st = ctx.timestep(ua, None, ub, tbs.PREC_MIXED, rtol, 4000)
+        assert st["converged"] and st["rel_res_fp64"] <= rtol, st
+        b = op.rhs(host(ua), None, n, tau, bc)
+        assert solvers.rel_residual(lambda v: op.apply(v, n, h, tau, bc), b, host(ub)) <= rtol * 1.01
+        ua, ub = ub, ua
