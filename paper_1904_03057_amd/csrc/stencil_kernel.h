@@ -340,6 +340,17 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
       if (active) stage_plane(ph % PF);
       __syncthreads();
       if (k + PF < kend) fetch(k + PF, ph % PF);
+      // RESID: b at the points of the output plane this iteration completes, loaded now so the
+      // loads are in flight during the filter passes instead of at the output
+      double bpre[MODE == M_RESID ? RPW : 1];
+      if constexpr (MODE == M_RESID) {
+        const int o = k - N;
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+          const int gy = y0 + wave * RPW + i;
+          bpre[i] = (o >= z0 && colown && gy < ny) ? a.bvec[(int64_t)o * plane + (int64_t)gy * nx + gxo] : 0.0;
+        }
+      }
       if (active) {
         if constexpr (CG) {
           const int qs = ((k % QD) + QD) % QD;
@@ -508,7 +519,7 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
                   b0 = (double)accb[RR ? so : 0][RR ? i : 0];
                   ((double*)a.out1)[gi] = b0;  // the step's right-hand side, as the rhs kernel forms it
                 } else {
-                  b0 = a.bvec[gi];
+                  b0 = bpre[MODE == M_RESID ? i : 0];
                 }
                 const double b = b0 * a.rscale;
                 const double r = b - (double)val * a.rscale;
