@@ -164,7 +164,7 @@ struct tbs_ctx {
   int64_t cgrid[3];
   // learned-guess backoff (opts.guess_backoff): consecutive rejections, steps left to skip
   int guess_rejects, guess_wait;
-  hipEvent_t cost_ev[4];  // guess_backoff 2: network + test start / end; step end or CG loop start / end
+  hipEvent_t cost_ev[4];  // guess_backoff 2: network + test start / end, CG loop start / end
   bool cost_ev_made;
   int cgf_pend;  // host copy of the pending x-update count of the one-kernel CG (for its byte count)
   // CG session state (tbs_cg_begin / tbs_cg_step)
