@@ -167,6 +167,7 @@ struct tbs_ctx {
   hipEvent_t cost_ev[4];  // guess_backoff 2: network + test start / end, CG loop start / end
   bool cost_ev_made;
   int cgf_pend;  // host copy of the pending x-update count of the one-kernel CG (for its byte count)
+  bool cgf_xzero;  // host copy of Scalars::xzero for the refinement's inner solve (same use)
   // CG session state (tbs_cg_begin / tbs_cg_step)
   int cg_active, cg_dt, cg_enq;
   void* cg_x;
@@ -814,8 +815,11 @@ static int cgf_async(tbs_ctx* c, const CgArrays& A, int dt, int k) {
   // first iteration: read r, write r, p, q; later: read r, q, p_old, write r, p, q, and on the
   // iterations that advance x also read x, p_{k-2} and write x
   const int pend = k == 0 ? 0 : c->cgf_pend;
-  const double b1 = (double)c->N * (k == 0 ? 3 * tc + tp : (pend == 2 ? 6 * tc + 3 * tp : 2 * (2 * tc + tp)));
+  // (the first x update of the refinement's inner solve does not read x = 0)
+  const double xr = (pend == 2 && c->cgf_xzero) ? 0 : tc;
+  const double b1 = (double)c->N * (k == 0 ? 3 * tc + tp : (pend == 2 ? 5 * tc + xr + 3 * tp : 2 * (2 * tc + tp)));
   c->cgf_pend = (pend == 2 ? 0 : pend) + 1;
+  if (pend == 2) c->cgf_xzero = false;
   int ps = prof_begin(c, dt == 0 ? 15 : (dt == 1 ? 11 : 12), k, b1);
   HIPCHK(launch_cgf(a, c->n, c->bc, dt, c->st));
   prof_end(c, ps);
@@ -1327,15 +1331,20 @@ extern "C" int tbs_timestep(tbs_ctx* c, const double* u_prev, const double* q, d
       // a bf16-stored direction limits the attainable inner accuracy: never ask it for less than 1e-4
       const double eta = std::max(std::max(c->opts.inner_rtol, dt == 2 ? 1e-4 : 0.0), 0.5 * rtol / rel);
       expect_pass = (rel * eta <= rtol);
-      HIPCHK(launch_fill(d32, 1, c->N, c->st));
-      HIPCHK(launch_finalize(FIN_INIT, part0(c), part0(c), stencil_blocks(base_args(c), M_RESID, 8, c->n, c->bc), scal(c, SC_CG),
-                             eta, c->st));
+      // the one-kernel iteration takes d = 0 as given (not read until its first x update writes d,
+      // nor by the refinement update if no update came), so d needs no zero fill
+      const bool dzero = c->opts.fused_cg != 0;
+      if (!dzero) HIPCHK(launch_fill(d32, 1, c->N, c->st));
+      HIPCHK(launch_finalize(dzero ? FIN_INIT_XZERO : FIN_INIT, part0(c), part0(c),
+                             stencil_blocks(base_args(c), M_RESID, 8, c->n, c->bc), scal(c, SC_CG), eta, c->st));
+      c->cgf_xzero = dzero;
       int nit = 0;
       const int cap = std::min(c->opts.inner_max_iter, std::max(1, max_iter - total));
       // the inner solve's last x update is left pending and applied by the refinement update:
       // u_next = (u_next or u_prev) + (d + alpha p) in one pass over the arrays
       if (costed) HIPCHK(hipEventRecord(c->cost_ev[2], c->st));
       int irc = cg_loop(c, A, dt, 0, cap, &nit, true);
+      c->cgf_xzero = false;
       if (costed && (rc = cost_lap(c, &t_cg))) return rc;
       total += nit;
       expect_pass = expect_pass && irc == TBS_OK;

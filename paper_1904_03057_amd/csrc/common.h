@@ -30,6 +30,9 @@ struct Scalars {
   // x updates still to apply: 1 = alpha p_{nit-1}; 2 (one-kernel FP32 CG, which advances x every
   // second iteration) = alpha2 p_{nit-2}, then alpha p_{nit-1}
   int pending;
+  // 1: x is zero and not read (set by FIN_INIT_XZERO; the first x update writes it, the x-update
+  // kernels and the refinement update take it as zero until then)
+  int xzero;
 };
 static_assert(sizeof(Scalars) <= 256, "a Scalars slot of the workspace is 256 bytes");
 

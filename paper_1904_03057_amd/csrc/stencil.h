@@ -124,7 +124,7 @@ hipError_t launch_guess_combine(double* x, const double* u, const float* du, int
 
 // finalize kernels (single block, fixed-order reduction of partial sums)
 enum FinOp { FIN_INIT = 0, FIN_ALPHA = 1, FIN_BETA = 2, FIN_DOT = 3, FIN_NORMS = 4, FIN_CLEAR_PENDING = 5,
-             FIN_FUSED = 6 };
+             FIN_FUSED = 6, FIN_INIT_XZERO = 7 };  // FIN_INIT_XZERO: FIN_INIT for x = 0 left unwritten
 // Reduces the per-block partial sums p0 (and p1, p2, p3 where the op uses them) in a fixed order
 // and updates the CG scalars.  FIN_FUSED takes p.q, r.q, q.q and r.r of a CGF launch.
 hipError_t launch_finalize(int op, const double* p0, const double* p1, int count, Scalars* s, double rtol,

@@ -192,6 +192,7 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
   // iteration while it is read and written half as often
   const int npend = CG ? a.scal->pending : 0;
   const bool xupd = CG && a.io0 != nullptr && !a.first && (FUSED ? npend == 2 : npend != 0);
+  const bool xload = xupd && !(CG && a.scal->xzero);  // x known to be zero: not read
   const Tc alpha2 = FUSED ? (Tc)a.scal->alpha2 : (Tc)0;
   const Tc tauc = (Tc)a.t.tau;
 
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(64 * WX * WY) __attribute__((amdgpu_waves_per_eu(BC
           if (!a.first) pa[sl][v] = *(const Raw*)((const Tin*)a.in1 + gi);
           if (FUSED && !a.first) pq[FUSED ? sl : 0][FUSED ? v : 0] = *(const RawC*)((const Tc*)a.in2 + gi);
           if (v < NVC && xupd && inchunk && ((own >> v) & 1u)) {
-            px[sl][v < NVC ? v : 0] = *(const RawC*)((const Tc*)a.io0 + gi);
+            if (xload) px[sl][v < NVC ? v : 0] = *(const RawC*)((const Tc*)a.io0 + gi);
             if (FUSED) pp2[FUSED ? sl : 0][FUSED && v < NVC ? v : 0] = *(const Raw*)((const Tin*)a.out1 + gi);
           }
         }

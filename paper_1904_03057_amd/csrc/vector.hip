@@ -109,12 +109,16 @@ __global__ __launch_bounds__(256) void flush_kernel(T* __restrict__ x, const Tp*
                                                     const Tp* __restrict__ p1, int64_t n, const Scalars* s) {
   const int np = s->pending;
   if (!np) return;
+  const bool xz = s->xzero;
   const T alpha = (T)s->alpha, alpha2 = (T)s->alpha2;
   const Tp* p = (s->nit & 1) ? p1 : p0;
   const Tp* pp = (s->nit & 1) ? p0 : p1;
   const int64_t stride = (int64_t)gridDim.x * 256;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride)
-    x[i] = apply_pending<T, Tp>(x[i], np, alpha, alpha2, p, pp, i);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+    T x0 = (T)0;
+    if (!xz) x0 = x[i];
+    x[i] = apply_pending<T, Tp>(x0, np, alpha, alpha2, p, pp, i);
+  }
 }
 
 // out = base + scale (d + the pending updates), the FP32 part formed exactly as flush_kernel forms it
@@ -123,12 +127,15 @@ __global__ __launch_bounds__(256) void refine_add_kernel(double* out, const doub
                                                          const Tp* __restrict__ p0, const Tp* __restrict__ p1,
                                                          int64_t n, const Scalars* s, double scale) {
   const int np = s->pending;
+  const bool dz = s->xzero;  // d was never written: zero
   const float alpha = (float)s->alpha, alpha2 = (float)s->alpha2;
   const Tp* p = (s->nit & 1) ? p1 : p0;
   const Tp* pp = (s->nit & 1) ? p0 : p1;
   const int64_t stride = (int64_t)gridDim.x * 256;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
-    const float x = apply_pending<float, Tp>(d[i], np, alpha, alpha2, p, pp, i);
+    float d0 = 0.f;
+    if (!dz) d0 = d[i];
+    const float x = apply_pending<float, Tp>(d0, np, alpha, alpha2, p, pp, i);
     out[i] = fma(scale, (double)x, base[i]);
   }
 }
@@ -235,9 +242,11 @@ __global__ __launch_bounds__(1024) void finalize_kernel(int op, const double* __
   if (threadIdx.x != 0) return;
   const double v0 = r0[0], v1 = r1[0], v2 = r2[0], v3 = r3[0];
   switch (op) {
-    case FIN_INIT: {
+    case FIN_INIT:
+    case FIN_INIT_XZERO: {
       s->rr = v0; s->rr0 = v0; s->bb = v1; s->tol2 = rtol * rtol * v1;
       s->nit = 0; s->status = 0; s->pending = 0; s->alpha = 0.0; s->alpha2 = 0.0; s->beta = 0.0;
+      s->xzero = (op == FIN_INIT_XZERO);
       int done = (v1 == 0.0) || (v0 <= s->tol2);
       if (!isfinite(v0) || !isfinite(v1)) { s->status = -4; done = 1; }
       s->done = done;
@@ -264,7 +273,7 @@ __global__ __launch_bounds__(1024) void finalize_kernel(int op, const double* __
       // alpha from the explicit r_k.r_k; r_{k+1}.r_{k+1} = r.r - 2 alpha r.q + alpha^2 q.q (one step
       // ahead, restarted from the explicit value every iteration) gives beta and the stopping test.
       // The kernel applied the pending x updates only if there were two; this iteration's is added.
-      if (s->pending == 2) s->pending = 0;
+      if (s->pending == 2) { s->pending = 0; s->xzero = 0; }  // x was written
       s->pq = v0;
       if (!(v0 > 0.0) || !isfinite(v0) || !isfinite(v1) || !isfinite(v2) || !isfinite(v3)) {
         s->status = -4; s->done = 1; break;
