@@ -1,7 +1,8 @@
 """The fused right-hand side and first residual of a source-free refined step (one pass over u^k
 forming b = M u^k and b - A u^k) against the separate rhs and residual kernels: the steps agree bit
 for bit, and their answers pass the oracle's residual test.  Also the sweeps' convergence checks
-(norms only when a check is expected to pass) at tolerances down to 1e-12."""
+(norms only when a check is expected to pass) at tolerances down to 1e-12, and that no step reads
+workspace contents it did not write (the inner correction starts as zero without a fill)."""
 import numpy as np
 import pytest
 
@@ -72,3 +73,33 @@ def test_refined_steps_convergence_checks(n, grid, bc, rtol):
         b = op.rhs(host(ua), None, n, tau, bc)
         assert solvers.rel_residual(lambda v: op.apply(v, n, h, tau, bc), b, host(ub)) <= rtol * 1.01
         ua, ub = ub, ua
+
+
+@pytest.mark.parametrize("prec", ["MIXED", "MIXED_BF16"])
+@pytest.mark.parametrize("n,grid,bc", [(3, (70, 22, 20), "dirichlet"), (1, (23, 17, 9), "periodic")])
+def test_refined_steps_read_no_stale_workspace(n, grid, bc, prec):
+    # the inner solve's correction d starts as zero without being filled (its first update writes
+    # it, the refinement update takes it as zero until then): steps on a workspace filled with NaN
+    # bytes before every step equal the steps on a fresh one bit for bit
+    import torch
+    print("stale", n, grid, bc, prec, flush=True)
+    h = tuple(1.0 / N for N in grid)
+    P = getattr(tbs, "PREC_" + prec)
+    u = normal_field(grid[::-1], 120 + n)
+    outs = []
+    for poison in (False, True):
+        ctx = tbs.Context(grid, n, h, 2e-3, bc)
+        ws = ctx.ensure_workspace(P)
+        ua, ub = dev(u), dev(np.zeros(grid[::-1]))
+        res = []
+        for rtol in (1e-9, 1e-3, 1e-12):  # 1e-3: a short inner solve, possibly with no x update
+            if poison:
+                ws.fill_(0xFF)
+                torch.cuda.synchronize()
+            st = ctx.timestep(ua, None, ub, P, rtol, 4000)
+            assert st["converged"], st
+            res.append((host(ub), st["iters"], st["sweeps"]))
+            ua, ub = ub, ua
+        outs.append(res)
+    for (a, ia, sa), (b, ib, sb) in zip(*outs):
+        assert np.array_equal(a, b) and np.all(np.isfinite(a)) and ia == ib and sa == sb
